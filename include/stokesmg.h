@@ -1,0 +1,211 @@
+/*
+ * stokesmg — coupled multigrid for the discretized generalized Stokes problem
+ * on MI355X (gfx950), C ABI.
+ *
+ * Problem (paper, Section 1): -Lap u + beta u + grad p = f, div u = g in the
+ * unit square, u = 0 on the boundary, int p = int g = 0, discretized with
+ * Taylor-Hood P2-P1 elements (Section 2) on a uniformly refined grid of
+ * N x N squares, each cut by the diagonal from its lower-left to its
+ * upper-right corner.  The discrete system (matrix form, Section 2) is
+ *
+ *        [ A  B^T ] [u]   [f]      A = K + beta M  (both velocity components)
+ *        [ B   0  ] [p] = [g],     B_ij = (div psi_j, phi_i)
+ *
+ * and is solved by the coupled multigrid iterate of Section 3 with the
+ * normal-equation or Uzawa-type smoother of Section 4, preconditioned by
+ * L = diag(Ahat, Shat), Ahat = diag A, Shat = diag(B Ahat^-1 B^T) (Section 6).
+ *
+ * SIGN CONVENTION.  Matrices follow the variational form of Section 2, whose
+ * coupling term is +(p, div v).  Integrating by parts, the returned pressure
+ * p is therefore the NEGATIVE of the p of the strong form as printed in
+ * Section 1 (the two forms of the paper differ in this sign).
+ *
+ * DATA LAYOUT.  All vectors are caller-owned DEVICE pointers on the device
+ * that was current at smg_setup, in the lattice layout of their level
+ * (N_l = n0 * 2^l cells per side, M_l = 2 N_l + 1):
+ *   velocity  double u[2][M_l][M_l]   component, y index b, x index a; P2 node
+ *                                     (a, b) sits at (a/(2N_l), b/(2N_l)).
+ *                                     Even/even = vertices, odd entries = edge
+ *                                     midpoints.  Entries on the boundary are
+ *                                     ignored on input and written 0 on output.
+ *   pressure  double p[N_l+1][N_l+1] y index j, x index i; vertex (i/N_l, j/N_l).
+ * Load vectors (right-hand sides) use the same layout: fu holds (f, psi) for
+ * each interior P2 node, gp holds (g, phi) for each P1 node.  The library
+ * never frees or retains caller pointers.  Outputs must not alias inputs
+ * unless an entry point says so.
+ *
+ * STREAMS AND THREADS.  Every entry point enqueues on the given stream and
+ * returns without waiting, except smg_setup, smg_destroy, smg_solve and
+ * smg_solve_mixed, which synchronize the stream.  A handle owns scratch
+ * buffers: calls on one handle must not overlap in time (use one stream per
+ * handle, or one handle per concurrent stream).
+ *
+ * ERRORS.  Every function returns an int status.  0 = SMG_OK.  Negative values
+ * are hard errors and leave outputs unspecified; positive values are soft
+ * results with valid outputs.  smg_last_error() gives a thread-local message.
+ */
+#ifndef STOKESMG_H
+#define STOKESMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smg_hier* smg_t;
+typedef void* smg_stream_t; /* a hipStream_t; NULL = the default stream */
+
+enum {
+  SMG_OK = 0,
+  SMG_EINVAL = -1,      /* bad argument: N not n0 * 2^L, beta < 0, NULL, bad level */
+  SMG_EHIP = -2,        /* a HIP runtime call failed */
+  SMG_ENOMEM = -3,      /* device allocation failed */
+  SMG_ESINGULAR = -4,   /* coarsest-grid matrix numerically singular */
+  SMG_NOCONV = 1,       /* maxit reached; outputs hold the last iterate */
+  SMG_DIVERGED = 2,     /* relative residual above 1e6; last iterate returned */
+  SMG_ENONFINITE = 3    /* NaN or Inf in the residual; last iterate returned */
+};
+
+enum { SMG_SMOOTHER_NE = 0, SMG_SMOOTHER_UZAWA = 1 };
+
+/* Solver parameters (Sections 3, 4 and 6). */
+typedef struct {
+  int smoother;   /* SMG_SMOOTHER_NE (normal equation) or SMG_SMOOTHER_UZAWA   */
+  double tau;     /* damping: 0.35 (normal equation), 0.8 (Uzawa)               */
+  double sigma;   /* Uzawa pressure damping: 0.8                                */
+  int nu_pre;     /* smoothing steps before the coarse-grid correction          */
+  int nu_post;    /* smoothing steps after it                                   */
+  int gamma;      /* 1 = V-cycle, 2 = W-cycle                                    */
+  int n0;         /* cells per side of the coarsest grid (>= 2); solved exactly */
+} smg_params;
+
+/* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2. */
+int smg_default_params(smg_params* prm);
+
+/* Thread-local description of the last error (never NULL). */
+const char* smg_last_error(void);
+
+/*
+ * Build the hierarchy for N cells per side (N = n0 * 2^L, L >= 0) and
+ * beta >= 0 on the current device: per-level stencil coefficients, the
+ * Shat^-1 arrays (Section 6, preconditioner), work vectors, and the inverse of
+ * the coarsest-grid saddle matrix bordered by the mean-zero constraint
+ * m^T p = 0, m_i = int phi_i (Section 3: level 0 is solved exactly).
+ * Synchronous.  Errors: SMG_EINVAL, SMG_ENOMEM, SMG_ESINGULAR, SMG_EHIP.
+ */
+int smg_setup(int N, double beta, const smg_params* prm, smg_t* out);
+int smg_destroy(smg_t h);
+
+/* Levels are numbered 0 (coarsest, n0 cells) .. L (finest, N cells). */
+int smg_num_levels(smg_t h);
+int smg_level_size(smg_t h, int level, int* N, int64_t* n_velocity, int64_t* n_pressure);
+
+/*
+ * Load vectors of P2 / P1 interpolants (Section 2, right-hand side):
+ *   fu = (f, psi_j) at interior P2 nodes, both components, from nodal values
+ *        f_nodal[2][M][M] given at ALL lattice points (boundary included);
+ *   gp = (g, phi_i) at all P1 nodes, from nodal g_nodal[N+1][N+1].
+ * Either output may be NULL to skip it.
+ */
+int smg_load(smg_t h, int level, const double* f_nodal, const double* g_nodal,
+             double* fu, double* gp, smg_stream_t s);
+
+/*
+ * Velocity mass: y = M u (both components, M the P2 mass matrix).  If
+ * all_nodes = 0 the rows are the interior nodes (boundary rows written 0) and
+ * u is read at interior nodes only; if all_nodes = 1 the rows are all
+ * lattice points (the transpose of the load map of smg_load: dL/df_nodal from
+ * dL/dfu).
+ */
+int smg_mass(smg_t h, int level, int all_nodes, const double* u, double* y, smg_stream_t s);
+
+/* Pressure mass: gp = M_P g (P1 mass matrix, all nodes). */
+int smg_pressure_mass(smg_t h, int level, const double* g, double* gp, smg_stream_t s);
+
+/* y = calA x: yu = A u + B^T p, yp = B u (matrix form, Section 2). */
+int smg_apply(smg_t h, int level, const double* u, const double* p,
+              double* yu, double* yp, smg_stream_t s);
+
+/*
+ * Residual r = F - calA x (Section 3, defect).  If norm2 is not NULL it
+ * receives (device pointer, one double) the squared Euclidean norm over the
+ * interior velocity and all pressure entries, reduced in a fixed order.
+ */
+int smg_residual(smg_t h, int level, const double* fu, const double* gp,
+                 const double* u, const double* p, double* ru, double* rp,
+                 double* norm2, smg_stream_t s);
+
+/* nsteps smoothing steps of the configured smoother (Section 4), in place on (u, p). */
+int smg_smooth(smg_t h, int level, int nsteps, const double* fu, const double* gp,
+               double* u, double* p, smg_stream_t s);
+
+/* Restriction I_k^{k-1} = (I_{k-1}^k)^T (Section 3) from level fine_level to
+ * fine_level - 1.  Coarse outputs use the coarse layout. */
+int smg_restrict(smg_t h, int fine_level, const double* ru, const double* rp,
+                 double* rcu, double* rcp, smg_stream_t s);
+
+/* Prolongation and add: (u, p) += I_{k-1}^k (zu, zp), the canonical embedding
+ * of the coarse P2 / P1 functions (Section 3). */
+int smg_prolong_add(smg_t h, int fine_level, const double* zcu, const double* zcp,
+                    double* u, double* p, smg_stream_t s);
+
+/* Exact solve on level 0 with the bordered matrix (mean-free pressure result). */
+int smg_coarse_solve(smg_t h, const double* ru, const double* rp, double* zu, double* zp,
+                     smg_stream_t s);
+
+/* p <- p - (sum_i m_i p_i) / (sum_i m_i), m_i = int phi_i: the mean-zero
+ * representative of P_k (Section 1 fixes int p = 0). */
+int smg_project_mean(smg_t h, int level, double* p, smg_stream_t s);
+
+/* One iterate of Section 3 on the finest level (nu_pre smoothing steps,
+ * coarse-grid correction by gamma recursive iterates, nu_post steps),
+ * followed by the mean projection; in place on (u, p). */
+int smg_cycle(smg_t h, const double* fu, const double* gp, double* u, double* p,
+              smg_stream_t s);
+
+/*
+ * Solve calA x = F on the finest level to ||F - calA x|| <= rtol ||F|| (2-norm
+ * over interior velocity and all pressure entries) by repeated iterates.
+ * (u, p) are the initial guess on entry and the solution on return (mean-free
+ * pressure).  iters, relres and history (maxit doubles, relative residual
+ * after each iterate) may be NULL; they are HOST pointers.  Synchronous.
+ * Returns SMG_OK, SMG_NOCONV, SMG_DIVERGED or SMG_ENONFINITE (soft) or a
+ * hard error.
+ */
+int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxit,
+              double* u, double* p, int* iters, double* relres, double* history,
+              smg_stream_t s);
+
+/*
+ * Same as smg_solve, but each iterate is one FP32 multigrid cycle applied to
+ * the correction equation calA d = r, inside FP64 iterative refinement:
+ *   r = F - calA x (FP64); d = cycle_fp32(r) from d = 0 with the FP64 coarse
+ *   solve; x += d (FP64); pressure mean removed (FP64).
+ * iters counts outer refinement steps (= FP32 cycles).  Synchronous.
+ */
+int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, int maxit,
+                    double* u, double* p, int* iters, double* relres, double* history,
+                    smg_stream_t s);
+
+/*
+ * Single-precision cycle (exposed for testing the FP32 kernels): one iterate
+ * as in smg_cycle on float vectors of the same layout, coarsest grid solved
+ * in FP64.  In place on (u, p).
+ */
+int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
+                  smg_stream_t s);
+
+/*
+ * Deterministic dot products on a level (device result in out[0]):
+ *   which = 0: sum over both velocity components at interior lattice points,
+ *   which = 1: sum over all pressure nodes.
+ */
+int smg_dot(smg_t h, int level, int which, const double* a, const double* b, double* out,
+            smg_stream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOKESMG_H */

@@ -1,0 +1,795 @@
+// Host runtime and C ABI of the coupled Stokes multigrid (see include/stokesmg.h).
+//
+// A handle owns one hierarchy: per-level stencil coefficients and Shat^-1
+// arrays (Section 6 preconditioner), work vectors in FP64 and FP32, the
+// inverse of the bordered coarsest-grid matrix (Section 3: level 0 is solved
+// exactly) and the device-side convergence state of the solve loop.
+//
+// The solve loop runs one iterate per replay of a captured HIP graph; every
+// kernel of an iterate first reads a device flag and returns at once when
+// the loop has already converged, so the host enqueues several iterates
+// between synchronizations without changing the result.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "smg_internal.h"
+#include "stokesmg.h"
+
+namespace smg {
+#include "stencils.inc"
+}
+
+using namespace smg;
+using smg::smg_stencil::A_K;
+using smg::smg_stencil::A_M;
+using smg::smg_stencil::DIAG_K;
+using smg::smg_stencil::DIAG_M;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(SMG_EHIP, "%s: %s", #x, hipGetErrorString(e_));  \
+  } while (0)
+
+template <class T>
+struct Vec {
+  T* u = nullptr;  // [2][M][M]
+  T* p = nullptr;  // [N+1][N+1], directly after u
+};
+
+struct Level {
+  int N = 0;
+  int64_t n_u = 0, n_p = 0;  // lattice sizes: 2 M^2 and (N+1)^2
+  LevelCoef<double> c64{};
+  LevelCoef<float> c32{};
+  Vec<double> x, f, t;
+  Vec<float> x32, f32, t32;
+  double* partial = nullptr;  // one double per stencil tile
+  int ntiles = 0;
+};
+
+template <class T> struct Sel;
+template <> struct Sel<double> {
+  static LevelCoef<double>& c(Level& L) { return L.c64; }
+  static Vec<double>& x(Level& L) { return L.x; }
+  static Vec<double>& f(Level& L) { return L.f; }
+  static Vec<double>& t(Level& L) { return L.t; }
+};
+template <> struct Sel<float> {
+  static LevelCoef<float>& c(Level& L) { return L.c32; }
+  static Vec<float>& x(Level& L) { return L.x32; }
+  static Vec<float>& f(Level& L) { return L.f32; }
+  static Vec<float>& t(Level& L) { return L.t32; }
+};
+
+}  // namespace
+
+struct smg_hier {
+  int device = 0;
+  smg_params prm{};
+  double beta = 0;
+  int L = 0;
+  std::vector<Level> lv;
+  double* cinv = nullptr;  // column-major inverse of the bordered coarse matrix
+  int nc = 0;
+  SolveState* st = nullptr;        // device
+  SolveState* st_host = nullptr;   // pinned host mirror
+  double* hist = nullptr;          // device, hist_cap doubles
+  int hist_cap = 0;
+  double* red = nullptr;           // reduction scratch
+  int red_cap = 0;
+  double* fdots = nullptr;         // 2 doubles
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t g64 = nullptr, g32 = nullptr;
+  std::vector<void*> allocs;
+
+  template <class T>
+  T* alloc(int64_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * std::max<int64_t>(n, 1)) != hipSuccess) return nullptr;
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~smg_hier() {
+    // teardown: errors cannot be reported from a destructor
+    if (g64) (void)hipGraphExecDestroy(g64);
+    if (g32) (void)hipGraphExecDestroy(g32);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void* p : allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// coefficients (Section 2 matrices on a level, Section 6 diagonal)
+// ---------------------------------------------------------------------------
+
+void make_coef(int N, double beta, LevelCoef<double>& c, LevelCoef<float>& c32) {
+  const double h = 1.0 / N, bh2 = beta * h * h;
+  c.N = c32.N = N;
+  c.h = h;
+  c32.h = (float)h;
+  for (int k = 0; k < 4; ++k) {
+    for (int g = 0; g < 5; ++g) {
+      c.acoef[k][g] = A_K[k][g] + bh2 * A_M[k][g];
+      c32.acoef[k][g] = (float)c.acoef[k][g];
+    }
+    c.adinv[k] = 1.0 / (DIAG_K[k] + bh2 * DIAG_M[k]);
+    c32.adinv[k] = (float)c.adinv[k];
+  }
+}
+
+// Host application of calA with the same lattice stencils (used once, to
+// assemble the coarsest-grid matrix column by column).
+template <class T>
+void host_apply(int N, const LevelCoef<T>& c, const T* u, const T* p, T* yu, T* yp) {
+  const int M = 2 * N + 1, NP = N + 1;
+  const T h = c.h;
+  auto Ug = [&](int comp, int a, int b) -> T {
+    return (a > 0 && a < 2 * N && b > 0 && b < 2 * N) ? u[(size_t)comp * M * M + (size_t)b * M + a] : T(0);
+  };
+  auto Pg = [&](int i, int j) -> T {
+    return (i >= 0 && i <= N && j >= 0 && j <= N) ? p[(size_t)j * NP + i] : T(0);
+  };
+  for (int comp = 0; comp < 2; ++comp)
+    for (int b = 0; b < M; ++b)
+      for (int a = 0; a < M; ++a) {
+        T y = T(0);
+        if (a > 0 && a < 2 * N && b > 0 && b < 2 * N) {
+          const int cls = (a & 1) + 2 * (b & 1), i = a >> 1, j = b >> 1;
+          auto U = [&](int da, int db) -> T { return Ug(comp, a + da, b + db); };
+          auto C = [&](int g) -> T { return c.acoef[cls][g]; };
+          auto P = [&](int di, int dj) -> T { return Pg(i + di, j + dj); };
+          switch (cls) {
+            case 0: y = SMG_A_ROW_V(U, C) + h * (comp == 0 ? SMG_BTX_ROW_V(P) : SMG_BTY_ROW_V(P)); break;
+            case 1: y = SMG_A_ROW_H(U, C) + h * (comp == 0 ? SMG_BTX_ROW_H(P) : SMG_BTY_ROW_H(P)); break;
+            case 2: y = SMG_A_ROW_E(U, C) + h * (comp == 0 ? SMG_BTX_ROW_E(P) : SMG_BTY_ROW_E(P)); break;
+            default: y = SMG_A_ROW_D(U, C) + h * (comp == 0 ? SMG_BTX_ROW_D(P) : SMG_BTY_ROW_D(P)); break;
+          }
+        }
+        yu[(size_t)comp * M * M + (size_t)b * M + a] = y;
+      }
+  for (int j = 0; j < NP; ++j)
+    for (int i = 0; i < NP; ++i) {
+      auto U0 = [&](int da, int db) -> T { return Ug(0, 2 * i + da, 2 * j + db); };
+      auto U1 = [&](int da, int db) -> T { return Ug(1, 2 * i + da, 2 * j + db); };
+      yp[(size_t)j * NP + i] = h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+    }
+}
+
+double p1_weight_host(int N, int i, int j) {
+  const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
+  if (!bi && !bj) return 1.0;
+  if (bi != bj) return 0.5;
+  return (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
+}
+
+// Bordered coarsest-grid matrix [[A, B^T, 0], [B, 0, m], [0, m^T, 0]] in the
+// compact order of the coarse-solve kernel, inverted by LU with partial pivoting.
+int build_coarse_inverse(int N0, const LevelCoef<double>& c, std::vector<double>& inv_colmajor) {
+  const int M = 2 * N0 + 1, ni = 2 * N0 - 1, nu = ni * ni, NP = N0 + 1;
+  const int nc = 2 * nu + NP * NP + 1;
+  std::vector<double> A((size_t)nc * nc, 0.0);  // row-major
+  std::vector<double> u(2 * M * M), p(NP * NP), yu(2 * M * M), yp(NP * NP);
+  auto lat_u = [&](int k) { const int comp = k / nu, q = k % nu; return comp * M * M + (1 + q / ni) * M + (1 + q % ni); };
+  for (int k = 0; k < nc - 1; ++k) {
+    std::fill(u.begin(), u.end(), 0.0);
+    std::fill(p.begin(), p.end(), 0.0);
+    if (k < 2 * nu) u[lat_u(k)] = 1.0; else p[k - 2 * nu] = 1.0;
+    host_apply<double>(N0, c, u.data(), p.data(), yu.data(), yp.data());
+    for (int r = 0; r < 2 * nu; ++r) A[(size_t)r * nc + k] = yu[lat_u(r)];
+    for (int r = 0; r < NP * NP; ++r) A[(size_t)(2 * nu + r) * nc + k] = yp[r];
+  }
+  const double h2 = 1.0 / ((double)N0 * N0);
+  for (int j = 0; j < NP; ++j)
+    for (int i = 0; i < NP; ++i) {
+      const double m = h2 * p1_weight_host(N0, i, j);
+      A[(size_t)(2 * nu + j * NP + i) * nc + (nc - 1)] = m;
+      A[(size_t)(nc - 1) * nc + (2 * nu + j * NP + i)] = m;
+    }
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  // LU with partial pivoting, then solve for the identity
+  std::vector<int> piv(nc);
+  for (int k = 0; k < nc; ++k) {
+    int r = k;
+    for (int q = k + 1; q < nc; ++q)
+      if (std::fabs(A[(size_t)q * nc + k]) > std::fabs(A[(size_t)r * nc + k])) r = q;
+    if (!(std::fabs(A[(size_t)r * nc + k]) > 1e-13 * amax))
+      return fail(SMG_ESINGULAR, "coarsest-grid matrix singular (pivot %d)", k);
+    piv[k] = r;
+    if (r != k)
+      for (int q = 0; q < nc; ++q) std::swap(A[(size_t)k * nc + q], A[(size_t)r * nc + q]);
+    const double d = A[(size_t)k * nc + k];
+    for (int q = k + 1; q < nc; ++q) {
+      const double l = A[(size_t)q * nc + k] / d;
+      A[(size_t)q * nc + k] = l;
+      if (l != 0.0)
+        for (int w = k + 1; w < nc; ++w) A[(size_t)q * nc + w] -= l * A[(size_t)k * nc + w];
+    }
+  }
+  inv_colmajor.assign((size_t)nc * nc, 0.0);
+  std::vector<double> e(nc);
+  for (int col = 0; col < nc; ++col) {
+    std::fill(e.begin(), e.end(), 0.0);
+    e[col] = 1.0;
+    for (int k = 0; k < nc; ++k) std::swap(e[k], e[piv[k]]);
+    for (int k = 0; k < nc; ++k)
+      for (int q = 0; q < k; ++q) e[k] -= A[(size_t)k * nc + q] * e[q];
+    for (int k = nc - 1; k >= 0; --k) {
+      for (int q = k + 1; q < nc; ++q) e[k] -= A[(size_t)k * nc + q] * e[q];
+      e[k] /= A[(size_t)k * nc + k];
+    }
+    // column `col` of the inverse: Inv[row][col] = e[row]; stored at [col * nc + row]
+    for (int row = 0; row < nc; ++row) inv_colmajor[(size_t)col * nc + row] = e[row];
+  }
+  return SMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// enqueue helpers
+// ---------------------------------------------------------------------------
+
+template <class T>
+StencilJob<T> job_of(Level& L) {
+  StencilJob<T> J{};
+  J.L = Sel<T>::c(L);
+  J.w_u = J.w_p = T(1);
+  return J;
+}
+
+// One smoothing step (Section 4) on (x, f) with scratch t.  zg: x is zero on
+// entry (its reads are skipped; the arithmetic is that of x = 0).
+template <class T>
+void smooth_step(const smg_params& prm, Level& L, Vec<T> x, Vec<T> f, Vec<T> t, bool zg,
+                 const int* done, hipStream_t s) {
+  if (prm.smoother == SMG_SMOOTHER_NE) {
+    // t = L^-1 (f - calA x);  x = x + tau L^-1 calA t
+    StencilJob<T> A = job_of<T>(L);
+    A.in_u = zg ? nullptr : x.u;
+    A.in_p = zg ? nullptr : x.p;
+    A.rhs_u = f.u; A.rhs_p = f.p;
+    A.diag_u = A.diag_p = 1;
+    A.out_u = t.u; A.out_p = t.p;
+    A.done = done;
+    launch_stencil<T>(A, ROWS_UP, s);
+    StencilJob<T> B = job_of<T>(L);
+    B.in_u = t.u; B.in_p = t.p;
+    B.base_u = zg ? nullptr : x.u;
+    B.base_p = zg ? nullptr : x.p;
+    B.w_u = B.w_p = T(-prm.tau);
+    B.diag_u = B.diag_p = 1;
+    B.out_u = x.u; B.out_p = x.p;
+    B.done = done;
+    launch_stencil<T>(B, ROWS_UP, s);
+  } else {
+    // t.u = u + tau Ahat^-1 (f - A u - B^T p)
+    StencilJob<T> A = job_of<T>(L);
+    A.in_u = zg ? nullptr : x.u;
+    A.in_p = zg ? nullptr : x.p;
+    A.rhs_u = f.u;
+    A.base_u = zg ? nullptr : x.u;
+    A.w_u = T(prm.tau);
+    A.diag_u = 1;
+    A.out_u = t.u;
+    A.done = done;
+    launch_stencil<T>(A, ROWS_U, s);
+    // t.p = dp = -sigma Shat^-1 (g - B t.u)
+    StencilJob<T> B = job_of<T>(L);
+    B.in_u = t.u;
+    B.rhs_p = f.p;
+    B.w_p = T(-prm.sigma);
+    B.diag_p = 1;
+    B.out_p = t.p;
+    B.done = done;
+    launch_stencil<T>(B, ROWS_P, s);
+    // x.u = t.u - tau Ahat^-1 B^T dp;  x.p = p + dp
+    StencilJob<T> C = job_of<T>(L);
+    C.in_p = t.p;
+    C.base_u = t.u;
+    C.w_u = T(prm.tau);
+    C.diag_u = 1;
+    C.rhs_p = t.p;
+    C.base_p = zg ? nullptr : x.p;
+    C.w_p = T(1);
+    C.out_u = x.u; C.out_p = x.p;
+    C.done = done;
+    launch_stencil<T>(C, ROWS_UP, s);
+  }
+}
+
+template <class T>
+void fill_vec(Level& L, Vec<T> v, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) launch_fill((double*)v.u, L.n_u + L.n_p, 0.0, s);
+  else launch_fill_f32((float*)v.u, L.n_u + L.n_p, 0.0f, s);
+}
+
+// Multigrid iterate of Section 3 on level l for (x, f); zg: x = 0 on entry.
+template <class T>
+void cycle_rec(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+  Level& L = H->lv[l];
+  if (l == 0) {
+    launch_coarse_solve<T>(L.N, H->nc, H->cinv, f.u, f.p, x.u, x.p, done, s);
+    return;
+  }
+  const smg_params& prm = H->prm;
+  Vec<T> t = Sel<T>::t(L);
+  bool z = zg;
+  if (z && prm.nu_pre == 0) {
+    fill_vec<T>(L, x, s);
+    z = false;
+  }
+  for (int k = 0; k < prm.nu_pre; ++k) {
+    smooth_step<T>(prm, L, x, f, t, z, done, s);
+    z = false;
+  }
+  // defect, restricted with the transposed embedding
+  StencilJob<T> R = job_of<T>(L);
+  R.in_u = x.u; R.in_p = x.p;
+  R.rhs_u = f.u; R.rhs_p = f.p;
+  R.out_u = t.u; R.out_p = t.p;
+  R.done = done;
+  launch_stencil<T>(R, ROWS_UP, s);
+  Level& C = H->lv[l - 1];
+  Vec<T> xc = Sel<T>::x(C), fc = Sel<T>::f(C);
+  launch_restrict<T>(C.N, t.u, t.p, fc.u, fc.p, nullptr, nullptr, done, s);
+  for (int g = 0; g < prm.gamma; ++g) cycle_rec<T>(H, l - 1, xc, fc, g == 0, done, s);
+  launch_prolong_add<T>(C.N, xc.u, xc.p, x.u, x.p, done, s);
+  for (int k = 0; k < prm.nu_post; ++k) smooth_step<T>(prm, L, x, f, t, false, done, s);
+}
+
+void project_mean(smg_hier* H, int l, double* p, const int* done, hipStream_t s) {
+  launch_project_mean(H->lv[l].N, p, H->red, done, s);
+}
+
+// residual of the finest level: optional write, partial sums in L.partial
+void top_residual(Level& L, const double* xu, const double* xp, const double* fu, const double* fp,
+                  double* ru, double* rp, const int* done, hipStream_t s) {
+  StencilJob<double> R = job_of<double>(L);
+  R.in_u = xu; R.in_p = xp;
+  R.rhs_u = fu; R.rhs_p = fp;
+  R.out_u = ru; R.out_p = rp;
+  R.partial = L.partial;
+  R.done = done;
+  launch_stencil<double>(R, ROWS_UP, s);
+}
+
+// one FP64 iterate of the solve loop on the internal finest-level vectors
+void enqueue_iter64(smg_hier* H, hipStream_t s) {
+  Level& T = H->lv[H->L];
+  const int* done = &H->st->done;
+  cycle_rec<double>(H, H->L, T.x, T.f, false, done, s);
+  project_mean(H, H->L, T.x.p, done, s);
+  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, nullptr, nullptr, done, s);
+  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+}
+
+// one refinement step: d = cycle_fp32(r), x += d, project, r = F - calA x
+void enqueue_iter_mixed(smg_hier* H, hipStream_t s) {
+  Level& T = H->lv[H->L];
+  const int* done = &H->st->done;
+  launch_cast_f64_f32(T.t.u, T.f32.u, T.n_u + T.n_p, done, s);
+  cycle_rec<float>(H, H->L, T.x32, T.f32, true, done, s);
+  launch_axpy_f32(T.x.u, T.x32.u, T.n_u + T.n_p, done, s);
+  project_mean(H, H->L, T.x.p, done, s);
+  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, T.t.u, T.t.p, done, s);
+  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+}
+
+int capture(smg_hier* H, void (*fn)(smg_hier*, hipStream_t), hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+  fn(H, H->cap_stream);
+  HIPCHK(hipStreamEndCapture(H->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(SMG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return SMG_OK;
+}
+
+int check_level(smg_hier* H, int level) {
+  if (!H) return fail(SMG_EINVAL, "null handle");
+  if (level < 0 || level > H->L) return fail(SMG_EINVAL, "level %d outside 0..%d", level, H->L);
+  HIPCHK(hipSetDevice(H->device));
+  return SMG_OK;
+}
+
+int launch_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SMG_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+  return SMG_OK;
+}
+
+// the solve loop shared by the FP64 and the mixed-precision variants
+int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, double rtol, int maxit,
+              double* u, double* p, int* iters, double* relres, double* history, hipStream_t s) {
+  if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
+  if (!(rtol >= 0) || maxit < 0) return fail(SMG_EINVAL, "bad rtol / maxit");
+  HIPCHK(hipSetDevice(H->device));
+  Level& T = H->lv[H->L];
+  if (maxit > H->hist_cap) {
+    double* nh = H->alloc<double>(maxit);
+    if (!nh) return fail(SMG_ENOMEM, "history buffer");
+    H->hist = nh;
+    H->hist_cap = maxit;
+  }
+  hipGraphExec_t* gexec = mixed ? &H->g32 : &H->g64;
+  if (!*gexec) {
+    int rc = capture(H, mixed ? enqueue_iter_mixed : enqueue_iter64, gexec);
+    if (rc) return rc;
+  }
+  const size_t bu = sizeof(double) * T.n_u, bp = sizeof(double) * T.n_p;
+  HIPCHK(hipMemcpyAsync(T.f.u, fu, bu, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(T.f.p, gp, bp, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(T.x.u, u, bu, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(T.x.p, p, bp, hipMemcpyDeviceToDevice, s));
+  {
+    // boundary entries of the caller's guess are ignored: x.u <- 0 + 1 * (x.u - 0)
+    // on interior rows and 0 on boundary rows (reads only the own entry)
+    StencilJob<double> Z = job_of<double>(T);
+    Z.rhs_u = T.x.u;
+    Z.out_u = T.x.u;
+    launch_stencil<double>(Z, ROWS_U, s);
+  }
+  project_mean(H, H->L, T.x.p, nullptr, s);
+  SolveState init{};
+  init.maxit = maxit;
+  init.tol2 = rtol * rtol;
+  *H->st_host = init;
+  HIPCHK(hipMemcpyAsync(H->st, H->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
+  launch_dot(T.N, 0, T.f.u, T.f.u, H->red, H->fdots, s);
+  launch_dot(T.N, 1, T.f.p, T.f.p, H->red, H->fdots + 1, s);
+  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, mixed ? T.t.u : nullptr, mixed ? T.t.p : nullptr,
+               nullptr, s);
+  launch_init_state(T.partial, T.ntiles, H->fdots, H->st, s);
+  int rc = launch_status("solve init");
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double rel_prev = H->st_host->relres;
+  int launched = 0, chunk = 2;
+  while (!H->st_host->done && launched < maxit) {
+    const int k = std::min(chunk, maxit - launched);
+    for (int q = 0; q < k; ++q) HIPCHK(hipGraphLaunch(*gexec, s));
+    launched += k;
+    HIPCHK(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rel = H->st_host->relres;
+    // predict the remaining iterates from the observed rate
+    double q = (rel > 0 && rel_prev > 0 && rel < rel_prev) ? std::pow(rel / rel_prev, 1.0 / k) : 0.9;
+    q = std::min(std::max(q, 1e-3), 0.99);
+    const double need = (rel > rtol && rtol > 0) ? std::log(rtol / rel) / std::log(q) : 1.0;
+    chunk = (int)std::min(64.0, std::max(1.0, std::ceil(need)));
+    rel_prev = rel;
+  }
+  // a solve with maxit = 0 never runs the loop: report the initial state
+  if (!H->st_host->done && maxit == 0) H->st_host->done = (H->st_host->relres <= rtol) ? 1 : 4;
+  HIPCHK(hipMemcpyAsync(u, T.x.u, bu, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(p, T.x.p, bp, hipMemcpyDeviceToDevice, s));
+  const int it = H->st_host->iters;
+  if (history && it > 0)
+    HIPCHK(hipMemcpyAsync(history, H->hist, sizeof(double) * it, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (iters) *iters = it;
+  if (relres) *relres = H->st_host->relres;
+  switch (H->st_host->done) {
+    case 1: return SMG_OK;
+    case 2: return fail(SMG_DIVERGED, "diverged after %d iterates (relres %g)", it, H->st_host->relres);
+    case 3: return fail(SMG_ENONFINITE, "non-finite residual after %d iterates", it);
+    default: return fail(SMG_NOCONV, "no convergence in %d iterates (relres %g)", it, H->st_host->relres);
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int smg_default_params(smg_params* prm) {
+  if (!prm) return fail(SMG_EINVAL, "null params");
+  prm->smoother = SMG_SMOOTHER_NE;
+  prm->tau = 0.35;
+  prm->sigma = 0.8;
+  prm->nu_pre = 2;
+  prm->nu_post = 2;
+  prm->gamma = 1;
+  prm->n0 = 2;
+  return SMG_OK;
+}
+
+const char* smg_last_error(void) { return g_err.c_str(); }
+
+int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
+  if (!out) return fail(SMG_EINVAL, "null output handle");
+  *out = nullptr;
+  smg_params prm;
+  if (prm_in) prm = *prm_in; else smg_default_params(&prm);
+  if (prm.smoother != SMG_SMOOTHER_NE && prm.smoother != SMG_SMOOTHER_UZAWA)
+    return fail(SMG_EINVAL, "unknown smoother %d", prm.smoother);
+  if (!(prm.tau > 0) || !(prm.sigma > 0)) return fail(SMG_EINVAL, "tau and sigma must be > 0");
+  if (prm.nu_pre < 0 || prm.nu_post < 0 || prm.nu_pre > 64 || prm.nu_post > 64)
+    return fail(SMG_EINVAL, "smoothing steps must be in 0..64");
+  if (prm.gamma != 1 && prm.gamma != 2) return fail(SMG_EINVAL, "gamma must be 1 or 2");
+  if (prm.n0 < 2 || prm.n0 > 8) return fail(SMG_EINVAL, "n0 must be in 2..8");
+  if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
+  int L = 0;
+  {
+    int n = N;
+    if (n < prm.n0) return fail(SMG_EINVAL, "N=%d below n0=%d", N, prm.n0);
+    while (n > prm.n0 && n % 2 == 0) { n /= 2; ++L; }
+    if (n != prm.n0) return fail(SMG_EINVAL, "N=%d is not n0 * 2^L (n0=%d)", N, prm.n0);
+    if (N > 8192) return fail(SMG_EINVAL, "N=%d too large", N);
+  }
+  smg_hier* H = new smg_hier();
+  H->prm = prm;
+  H->beta = beta;
+  H->L = L;
+  if (hipGetDevice(&H->device) != hipSuccess) { delete H; return fail(SMG_EHIP, "hipGetDevice"); }
+  H->lv.resize(L + 1);
+  int red_need = 8;
+  for (int l = 0; l <= L; ++l) {
+    Level& Lv = H->lv[l];
+    Lv.N = prm.n0 << l;
+    const int64_t M = 2 * Lv.N + 1;
+    Lv.n_u = 2 * M * M;
+    Lv.n_p = (int64_t)(Lv.N + 1) * (Lv.N + 1);
+    make_coef(Lv.N, beta, Lv.c64, Lv.c32);
+    const int64_t nv = Lv.n_u + Lv.n_p;
+    double* b64 = H->alloc<double>(3 * nv);
+    float* b32 = H->alloc<float>(3 * nv);
+    double* s64 = H->alloc<double>(Lv.n_p);
+    float* s32 = H->alloc<float>(Lv.n_p);
+    Lv.ntiles = stencil_tiles(Lv.N);
+    Lv.partial = H->alloc<double>(Lv.ntiles);
+    if (!b64 || !b32 || !s64 || !s32 || !Lv.partial) { delete H; return fail(SMG_ENOMEM, "level %d buffers", l); }
+    Vec<double>* v64[3] = {&Lv.x, &Lv.f, &Lv.t};
+    Vec<float>* v32[3] = {&Lv.x32, &Lv.f32, &Lv.t32};
+    for (int k = 0; k < 3; ++k) {
+      v64[k]->u = b64 + k * nv;
+      v64[k]->p = v64[k]->u + Lv.n_u;
+      v32[k]->u = b32 + k * nv;
+      v32[k]->p = v32[k]->u + Lv.n_u;
+    }
+    Lv.c64.sinv = s64;
+    Lv.c32.sinv = s32;
+    red_need = std::max(red_need, 2 * mean_blocks(Lv.N));
+    red_need = std::max(red_need, dot_blocks(Lv.N, 0));
+    red_need = std::max(red_need, dot_blocks(Lv.N, 1));
+  }
+  H->red = H->alloc<double>(red_need);
+  H->red_cap = red_need;
+  H->fdots = H->alloc<double>(2);
+  H->st = H->alloc<SolveState>(1);
+  H->hist_cap = 1000;
+  H->hist = H->alloc<double>(H->hist_cap);
+  if (!H->red || !H->fdots || !H->st || !H->hist) { delete H; return fail(SMG_ENOMEM, "scratch"); }
+  if (hipHostMalloc((void**)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+    H->st_host = nullptr;
+    delete H;
+    return fail(SMG_ENOMEM, "pinned state");
+  }
+  if (hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete H;
+    return fail(SMG_EHIP, "stream");
+  }
+  hipStream_t s = H->cap_stream;
+  for (int l = 0; l <= L; ++l) {
+    Level& Lv = H->lv[l];
+    launch_shat_inv<double>(Lv.N, Lv.c64.adinv, const_cast<double*>(Lv.c64.sinv), s);
+    launch_shat_inv<float>(Lv.N, Lv.c32.adinv, const_cast<float*>(Lv.c32.sinv), s);
+    for (int k = 0; k < 1; ++k) {
+      launch_fill(Lv.x.u, 3 * (Lv.n_u + Lv.n_p), 0.0, s);
+      launch_fill_f32(Lv.x32.u, 3 * (Lv.n_u + Lv.n_p), 0.0f, s);
+    }
+  }
+  std::vector<double> inv;
+  int rc = build_coarse_inverse(prm.n0, H->lv[0].c64, inv);
+  if (rc) { delete H; return rc; }
+  H->nc = (int)std::sqrt((double)inv.size());
+  H->cinv = H->alloc<double>((int64_t)inv.size());
+  if (!H->cinv) { delete H; return fail(SMG_ENOMEM, "coarse inverse"); }
+  if (hipMemcpyAsync(H->cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    delete H;
+    return fail(SMG_EHIP, "setup upload / kernels failed");
+  }
+  *out = H;
+  return SMG_OK;
+}
+
+int smg_destroy(smg_t h) {
+  if (!h) return SMG_OK;
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipDeviceSynchronize());
+  delete h;
+  return SMG_OK;
+}
+
+int smg_num_levels(smg_t h) { return h ? h->L + 1 : fail(SMG_EINVAL, "null handle"); }
+
+int smg_level_size(smg_t h, int level, int* N, int64_t* nvel, int64_t* npres) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  if (level < 0 || level > h->L) return fail(SMG_EINVAL, "level %d outside 0..%d", level, h->L);
+  const Level& L = h->lv[level];
+  if (N) *N = L.N;
+  if (nvel) *nvel = L.n_u;
+  if (npres) *npres = L.n_p;
+  return SMG_OK;
+}
+
+int smg_load(smg_t h, int level, const double* f_nodal, const double* g_nodal, double* fu,
+             double* gp, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)sv;
+  const int N = h->lv[level].N;
+  if (fu) {
+    if (!f_nodal) return fail(SMG_EINVAL, "null f_nodal");
+    launch_mass_u(N, 2, f_nodal, fu, s);
+  }
+  if (gp) {
+    if (!g_nodal) return fail(SMG_EINVAL, "null g_nodal");
+    launch_mass_p(N, g_nodal, gp, s);
+  }
+  return launch_status("smg_load");
+}
+
+int smg_mass(smg_t h, int level, int all_nodes, const double* u, double* y, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!u || !y) return fail(SMG_EINVAL, "null vector");
+  launch_mass_u(h->lv[level].N, all_nodes ? 1 : 0, u, y, (hipStream_t)sv);
+  return launch_status("smg_mass");
+}
+
+int smg_pressure_mass(smg_t h, int level, const double* g, double* gp, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!g || !gp) return fail(SMG_EINVAL, "null vector");
+  launch_mass_p(h->lv[level].N, g, gp, (hipStream_t)sv);
+  return launch_status("smg_pressure_mass");
+}
+
+int smg_apply(smg_t h, int level, const double* u, const double* p, double* yu, double* yp,
+              smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!u || !p || !yu || !yp) return fail(SMG_EINVAL, "null vector");
+  StencilJob<double> J = job_of<double>(h->lv[level]);
+  J.in_u = u; J.in_p = p;
+  J.w_u = J.w_p = -1.0;
+  J.out_u = yu; J.out_p = yp;
+  launch_stencil<double>(J, ROWS_UP, (hipStream_t)sv);
+  return launch_status("smg_apply");
+}
+
+int smg_residual(smg_t h, int level, const double* fu, const double* gp, const double* u,
+                 const double* p, double* ru, double* rp, double* norm2, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!fu || !gp || !u || !p || !ru || !rp) return fail(SMG_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)sv;
+  Level& L = h->lv[level];
+  top_residual(L, u, p, fu, gp, ru, rp, nullptr, s);
+  if (norm2) launch_reduce(L.partial, L.ntiles, norm2, s);
+  return launch_status("smg_residual");
+}
+
+int smg_smooth(smg_t h, int level, int nsteps, const double* fu, const double* gp, double* u,
+               double* p, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
+  if (nsteps < 0) return fail(SMG_EINVAL, "nsteps < 0");
+  Level& L = h->lv[level];
+  Vec<double> x{u, p}, f{const_cast<double*>(fu), const_cast<double*>(gp)};
+  for (int k = 0; k < nsteps; ++k) smooth_step<double>(h->prm, L, x, f, L.t, false, nullptr, (hipStream_t)sv);
+  return launch_status("smg_smooth");
+}
+
+int smg_restrict(smg_t h, int fine_level, const double* ru, const double* rp, double* rcu,
+                 double* rcp, smg_stream_t sv) {
+  int rc = check_level(h, fine_level);
+  if (rc) return rc;
+  if (fine_level < 1) return fail(SMG_EINVAL, "restriction needs fine_level >= 1");
+  if (!ru || !rp || !rcu || !rcp) return fail(SMG_EINVAL, "null vector");
+  launch_restrict<double>(h->lv[fine_level - 1].N, ru, rp, rcu, rcp, nullptr, nullptr, nullptr,
+                          (hipStream_t)sv);
+  return launch_status("smg_restrict");
+}
+
+int smg_prolong_add(smg_t h, int fine_level, const double* zcu, const double* zcp, double* u,
+                    double* p, smg_stream_t sv) {
+  int rc = check_level(h, fine_level);
+  if (rc) return rc;
+  if (fine_level < 1) return fail(SMG_EINVAL, "prolongation needs fine_level >= 1");
+  if (!zcu || !zcp || !u || !p) return fail(SMG_EINVAL, "null vector");
+  launch_prolong_add<double>(h->lv[fine_level - 1].N, zcu, zcp, u, p, nullptr, (hipStream_t)sv);
+  return launch_status("smg_prolong_add");
+}
+
+int smg_coarse_solve(smg_t h, const double* ru, const double* rp, double* zu, double* zp,
+                     smg_stream_t sv) {
+  int rc = check_level(h, 0);
+  if (rc) return rc;
+  if (!ru || !rp || !zu || !zp) return fail(SMG_EINVAL, "null vector");
+  launch_coarse_solve<double>(h->lv[0].N, h->nc, h->cinv, ru, rp, zu, zp, nullptr, (hipStream_t)sv);
+  return launch_status("smg_coarse_solve");
+}
+
+int smg_project_mean(smg_t h, int level, double* p, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!p) return fail(SMG_EINVAL, "null vector");
+  project_mean(h, level, p, nullptr, (hipStream_t)sv);
+  return launch_status("smg_project_mean");
+}
+
+int smg_cycle(smg_t h, const double* fu, const double* gp, double* u, double* p, smg_stream_t sv) {
+  int rc = check_level(h, 0);
+  if (rc) return rc;
+  if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)sv;
+  Vec<double> x{u, p}, f{const_cast<double*>(fu), const_cast<double*>(gp)};
+  cycle_rec<double>(h, h->L, x, f, false, nullptr, s);
+  project_mean(h, h->L, p, nullptr, s);
+  return launch_status("smg_cycle");
+}
+
+int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p, smg_stream_t sv) {
+  int rc = check_level(h, 0);
+  if (rc) return rc;
+  if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
+  Vec<float> x{u, p}, f{const_cast<float*>(fu), const_cast<float*>(gp)};
+  cycle_rec<float>(h, h->L, x, f, false, nullptr, (hipStream_t)sv);
+  return launch_status("smg_cycle_f32");
+}
+
+int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxit, double* u,
+              double* p, int* iters, double* relres, double* history, smg_stream_t sv) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  return run_solve(h, false, fu, gp, rtol, maxit, u, p, iters, relres, history, (hipStream_t)sv);
+}
+
+int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, int maxit,
+                    double* u, double* p, int* iters, double* relres, double* history,
+                    smg_stream_t sv) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  return run_solve(h, true, fu, gp, rtol, maxit, u, p, iters, relres, history, (hipStream_t)sv);
+}
+
+int smg_dot(smg_t h, int level, int which, const double* a, const double* b, double* out,
+            smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!a || !b || !out) return fail(SMG_EINVAL, "null vector");
+  if (which != 0 && which != 1) return fail(SMG_EINVAL, "which must be 0 or 1");
+  launch_dot(h->lv[level].N, which, a, b, h->red, out, (hipStream_t)sv);
+  return launch_status("smg_dot");
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal interface between the host runtime (smg_capi.hip) and the HIP
+// kernels (smg_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace smg {
+
+// Per-level constants of the operator (Section 2 matrices, Section 6
+// preconditioner), in the arithmetic type T of the kernels.
+template <class T>
+struct LevelCoef {
+  int N;             // cells per side
+  T acoef[4][5];     // A = K + beta h^2 M, grouped lattice taps per node class
+  T adinv[4];        // 1 / Ahat per node class (V, H, E, D)
+  T h;               // 1 / N (scales B and B^T)
+  const T* sinv;     // 1 / Shat at every pressure node, (N+1)^2
+};
+
+// One application of the generic fused stencil
+//   out = base + w * D * (rhs - calA in)          (D = L^-1 rows or identity)
+// on the velocity rows (ROWS & 1) and / or the pressure rows (ROWS & 2).
+// NULL pointers mean "zero" (in_u, in_p, rhs, base) or "skip" (out).
+// in_p_sub, if set, is subtracted from in_p on load (Uzawa pressure update).
+// If partial is set, each tile writes its sum of (rhs - calA in)^2 over the
+// rows it owns (interior velocity nodes, all pressure nodes).
+template <class T>
+struct StencilJob {
+  LevelCoef<T> L;
+  const T* in_u;
+  const T* in_p;
+  const T* in_p_sub;
+  const T* rhs_u;
+  const T* rhs_p;
+  const T* base_u;
+  const T* base_p;
+  T* out_u;
+  T* out_p;
+  T w_u, w_p;          // weights of the velocity / pressure rows
+  int diag_u, diag_p;  // 1: scale by Ahat^-1 / Shat^-1, 0: no scaling
+  double* partial;     // per-tile partial sums, or NULL
+  const int* done;     // if non-NULL and *done != 0 the launch does nothing
+};
+
+enum { ROWS_U = 1, ROWS_P = 2, ROWS_UP = 3 };
+
+// tile shape of the stencil kernels: TX x TY cells per workgroup
+struct TileShape { int tx, ty; };
+TileShape stencil_tile(int N);
+int stencil_tiles(int N);
+
+template <class T>
+void launch_stencil(const StencilJob<T>& J, int rows, hipStream_t s);
+
+// r_c = P^T r_f (velocity P2, pressure P1); also zero (xcu, xcp) if not NULL.
+template <class T>
+void launch_restrict(int Nc, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
+                     const int* done, hipStream_t s);
+// (u, p) += P (zu, zp)
+template <class T>
+void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
+                        hipStream_t s);
+// z = Cinv * [r; 0] on the coarsest grid (FP64 inverse, any T in / out)
+template <class T>
+void launch_coarse_solve(int N0, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
+                         T* zp, const int* done, hipStream_t s);
+
+// p <- p - (m . p) / sum(m); uses `partials` (>= mean_blocks(N) doubles x 2)
+int mean_blocks(int N);
+void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s);
+
+// Shat^-1 at setup
+template <class T>
+void launch_shat_inv(int N, const T* adinv_host4, T* sinv, hipStream_t s);
+
+// load vectors / masses
+// mode 0: interior rows from interior values; 1: all rows from interior values;
+// 2: interior rows from all values (load vectors of nodal data)
+void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s);
+void launch_mass_p(int N, const double* g, double* gp, hipStream_t s);
+
+// deterministic dots: which = 0 velocity interior lattice points, 1 pressure
+int dot_blocks(int N, int which);
+void launch_dot(int N, int which, const double* a, const double* b, double* partials,
+                double* out, hipStream_t s);
+// out[0] = sum of np partials (fixed order)
+void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
+
+// Convergence bookkeeping of the solve loop (device-side).
+struct SolveState {
+  int done;        // 0 running, 1 converged, 2 diverged, 3 non-finite, 4 maxit
+  int iters;
+  int maxit;
+  int pad;
+  double fnorm2;   // ||F||^2
+  double tol2;     // rtol^2
+  double relres;   // last relative residual
+};
+// reduce `np` partials to ||r||^2; record the iterate: iters++, history, done flags.
+void launch_check(const double* partials, int np, SolveState* st, double* hist, hipStream_t s);
+// set the initial state: ||F||^2 = fdots[0] + fdots[1], ||F - calA x0||^2 from
+// np residual partials; done = 1 if x0 already meets the tolerance.
+void launch_init_state(const double* rpartials, int np, const double* fdots, SolveState* st,
+                       hipStream_t s);
+
+// elementwise helpers
+void launch_fill(double* x, int64_t n, double v, hipStream_t s);
+void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
+void launch_cast_f64_f32(const double* a, float* b, int64_t n, const int* done, hipStream_t s);
+// x += (double) d ; both with n entries
+void launch_axpy_f32(double* x, const float* d, int64_t n, const int* done, hipStream_t s);
+
+}  // namespace smg

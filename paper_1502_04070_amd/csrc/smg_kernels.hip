@@ -1,0 +1,717 @@
+// HIP kernels (gfx950) of the coupled Stokes multigrid: matrix-free
+// application of the Taylor-Hood saddle operator on the uniformly refined
+// same-diagonal grid, the smoother passes of Section 4, the canonical
+// transfers of Section 3, the exact coarsest-grid solve, the pressure-mean
+// projection and deterministic reductions.
+//
+// Lattice layout of a level with N x N squares (M = 2N + 1):
+//   u[c][b][a], c = component, P2 node (a, b) at (a / 2N, b / 2N);
+//   p[j][i], P1 vertex (i / N, j / N).
+// Work decomposition: square (i, j) owns the lattice points (2i, 2j) (V),
+// (2i+1, 2j) (H), (2i, 2j+1) (E), (2i+1, 2j+1) (D) and the vertex (i, j); one
+// thread per square, TX x TY squares per workgroup, the input window with a
+// halo of one square staged in LDS.  All operators are HBM-bound (about 2-4
+// flop per byte); no matrix core work is involved.
+#include "smg_internal.h"
+
+namespace smg {
+#include "stencils.inc"
+using namespace smg_stencil;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD gets
+// a contiguous range of tiles (neighbouring tiles share halo lines in that
+// XCD's L2).
+__device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+// Sum over the workgroup (NT a multiple of 64); result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) s += red[k];
+  }
+  return s;
+}
+
+template <int CLS, class T, class FU, class FC>
+__device__ __forceinline__ T a_row(FU U, FC C) {
+  if constexpr (CLS == 0) return SMG_A_ROW_V(U, C);
+  else if constexpr (CLS == 1) return SMG_A_ROW_H(U, C);
+  else if constexpr (CLS == 2) return SMG_A_ROW_E(U, C);
+  else return SMG_A_ROW_D(U, C);
+}
+template <int CLS, class T, class FP>
+__device__ __forceinline__ T btx_row(FP P) {
+  if constexpr (CLS == 0) return SMG_BTX_ROW_V(P);
+  else if constexpr (CLS == 1) return SMG_BTX_ROW_H(P);
+  else if constexpr (CLS == 2) return SMG_BTX_ROW_E(P);
+  else return SMG_BTX_ROW_D(P);
+}
+template <int CLS, class T, class FP>
+__device__ __forceinline__ T bty_row(FP P) {
+  if constexpr (CLS == 0) return SMG_BTY_ROW_V(P);
+  else if constexpr (CLS == 1) return SMG_BTY_ROW_H(P);
+  else if constexpr (CLS == 2) return SMG_BTY_ROW_E(P);
+  else return SMG_BTY_ROW_D(P);
+}
+template <int CLS, class T, class FU>
+__device__ __forceinline__ T m_row(FU U) {
+  if constexpr (CLS == 0) return SMG_M_ROW_V(U);
+  else if constexpr (CLS == 1) return SMG_M_ROW_H(U);
+  else if constexpr (CLS == 2) return SMG_M_ROW_E(U);
+  else return SMG_M_ROW_D(U);
+}
+template <int CLS, class T, class FR>
+__device__ __forceinline__ T res_row(FR R) {
+  if constexpr (CLS == 0) return SMG_RES_ROW_V(R);
+  else if constexpr (CLS == 1) return SMG_RES_ROW_H(R);
+  else if constexpr (CLS == 2) return SMG_RES_ROW_E(R);
+  else return SMG_RES_ROW_D(R);
+}
+
+// ---------------------------------------------------------------------------
+// generic fused stencil: out = base + w D (rhs - calA in)
+// ---------------------------------------------------------------------------
+
+template <int CLS, class T, int WX, int WY, int PX, int PY, int ROWS>
+__device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY][WX],
+                                              T (*sp)[PX], int tx, int ty, int i, int j,
+                                              bool hu, bool hp, double& nrm) {
+  constexpr int DA = CLS & 1, DB = CLS >> 1;
+  const int N = J.L.N, M = 2 * N + 1;
+  const int a = 2 * i + DA, b = 2 * j + DB;
+  if (a > 2 * N || b > 2 * N) return;
+  const bool interior = (a > 0) && (a < 2 * N) && (b > 0) && (b < 2 * N);
+  const int la = 2 * tx + 2 + DA, lb = 2 * ty + 2 + DB;
+  auto C = [&](int g) -> T { return J.L.acoef[CLS][g]; };
+  auto P = [&](int di, int dj) -> T { return sp[ty + 1 + dj][tx + 1 + di]; };
+  const T dscale = J.diag_u ? J.L.adinv[CLS] : T(1);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    auto U = [&](int da, int db) -> T { return su[c][lb + db][la + da]; };
+    T y = T(0);
+    if (hu) y += a_row<CLS, T>(U, C);
+    if (hp) y += J.L.h * (c == 0 ? btx_row<CLS, T>(P) : bty_row<CLS, T>(P));
+    const size_t g = (size_t)c * M * M + (size_t)b * M + a;
+    const T r = (J.rhs_u ? J.rhs_u[g] : T(0)) - y;
+    if (interior) nrm += (double)r * (double)r;
+    if (J.out_u) {
+      const T v = (J.base_u ? J.base_u[g] : T(0)) + J.w_u * dscale * r;
+      J.out_u[g] = interior ? v : T(0);
+    }
+  }
+}
+
+template <class T, int TX, int TY, int ROWS>
+__device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
+  constexpr int NT = TX * TY;
+  constexpr int WX = 2 * TX + 4, WY = 2 * TY + 4;
+  constexpr int PX = TX + 2, PY = TY + 2;
+  __shared__ T su[2][WY][WX];
+  __shared__ T sp[PY][PX];
+  __shared__ double red[NT / 64];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int ntx = (N + TX) / TX;
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  const bool hu = J.in_u != nullptr;
+  const bool hp = (ROWS & ROWS_U) && J.in_p != nullptr;
+  if (hu) {
+    for (int e = tid; e < WX * WY; e += NT) {
+      const int la = e % WX, lb = e / WX;
+      const int a = 2 * i0 - 2 + la, b = 2 * j0 - 2 + lb;
+      const bool in = (a > 0) && (a < 2 * N) && (b > 0) && (b < 2 * N);
+      const size_t g = (size_t)b * M + a;
+      su[0][lb][la] = in ? J.in_u[g] : T(0);
+      su[1][lb][la] = in ? J.in_u[(size_t)M * M + g] : T(0);
+    }
+  }
+  if (hp) {
+    for (int e = tid; e < PX * PY; e += NT) {
+      const int li = e % PX, lj = e / PX;
+      const int i = i0 - 1 + li, j = j0 - 1 + lj;
+      T v = T(0);
+      if (i >= 0 && i <= N && j >= 0 && j <= N) {
+        v = J.in_p[(size_t)j * NP + i];
+        if (J.in_p_sub) v -= J.in_p_sub[(size_t)j * NP + i];
+      }
+      sp[lj][li] = v;
+    }
+  }
+  __syncthreads();
+  const int tx = tid % TX, ty = tid / TX;
+  const int i = i0 + tx, j = j0 + ty;
+  double nrm = 0.0;
+  if (i <= N && j <= N) {
+    if constexpr ((ROWS & ROWS_U) != 0) {
+      velocity_node<0, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
+      velocity_node<1, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
+      velocity_node<2, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
+      velocity_node<3, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
+    }
+    if constexpr ((ROWS & ROWS_P) != 0) {
+      const int la = 2 * tx + 2, lb = 2 * ty + 2;
+      auto U0 = [&](int da, int db) -> T { return su[0][lb + db][la + da]; };
+      auto U1 = [&](int da, int db) -> T { return su[1][lb + db][la + da]; };
+      const T y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
+      const size_t g = (size_t)j * NP + i;
+      const T r = (J.rhs_p ? J.rhs_p[g] : T(0)) - y;
+      nrm += (double)r * (double)r;
+      if (J.out_p) {
+        const T d = J.diag_p ? J.L.sinv[g] : T(1);
+        J.out_p[g] = (J.base_p ? J.base_p[g] : T(0)) + J.w_p * d * r;
+      }
+    }
+  }
+  if (J.partial) {
+    const double s = block_sum<NT>(nrm, red);
+    if (tid == 0) J.partial[tile] = s;
+  }
+}
+
+template <class T, int TX, int TY, int ROWS>
+__global__ __launch_bounds__(TX* TY) void k_stencil(StencilJob<T> J) {
+  if (J.done && *J.done) return;
+  stencil_tile<T, TX, TY, ROWS>(J, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+TileShape stencil_tile(int N) {
+  if (N >= 512) return {16, 16};
+  if (N >= 256) return {16, 8};
+  return {8, 8};
+}
+
+int stencil_tiles(int N) {
+  const TileShape t = stencil_tile(N);
+  return ((N + t.tx) / t.tx) * ((N + t.ty) / t.ty);
+}
+
+template <class T, int TX, int TY>
+static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s) {
+  const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
+  if (rows == ROWS_U)
+    k_stencil<T, TX, TY, ROWS_U><<<nb, TX * TY, 0, s>>>(J);
+  else if (rows == ROWS_P)
+    k_stencil<T, TX, TY, ROWS_P><<<nb, TX * TY, 0, s>>>(J);
+  else
+    k_stencil<T, TX, TY, ROWS_UP><<<nb, TX * TY, 0, s>>>(J);
+}
+
+template <class T>
+void launch_stencil(const StencilJob<T>& J, int rows, hipStream_t s) {
+  const TileShape t = stencil_tile(J.L.N);
+  if (t.tx == 16 && t.ty == 16)
+    launch_stencil_shape<T, 16, 16>(J, rows, s);
+  else if (t.tx == 16 && t.ty == 8)
+    launch_stencil_shape<T, 16, 8>(J, rows, s);
+  else
+    launch_stencil_shape<T, 8, 8>(J, rows, s);
+}
+template void launch_stencil<double>(const StencilJob<double>&, int, hipStream_t);
+template void launch_stencil<float>(const StencilJob<float>&, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// transfers (Section 3): one thread per coarse square
+// ---------------------------------------------------------------------------
+
+template <int CLS, class T>
+__device__ __forceinline__ void restrict_node(int Nc, int I, int J, const T* rfu, T* rcu, T* xcu) {
+  constexpr int CA = CLS & 1, CB = CLS >> 1;
+  const int A = 2 * I + CA, B = 2 * J + CB;
+  if (A > 2 * Nc || B > 2 * Nc) return;
+  const int Mc = 2 * Nc + 1, Mf = 4 * Nc + 1;
+  const bool interior = A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const T* rf = rfu + (size_t)c * Mf * Mf;
+    auto R = [&](int fa, int fb) -> T {
+      const int a = 2 * A + fa, b = 2 * B + fb;
+      return (a > 0 && a < Mf - 1 && b > 0 && b < Mf - 1) ? rf[(size_t)b * Mf + a] : T(0);
+    };
+    const T v = interior ? res_row<CLS, T>(R) : T(0);
+    const size_t g = (size_t)c * Mc * Mc + (size_t)B * Mc + A;
+    rcu[g] = v;
+    if (xcu) xcu[g] = T(0);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict(int Nc, const T* __restrict__ rfu,
+                                                  const T* __restrict__ rfp, T* rcu, T* rcp,
+                                                  T* xcu, T* xcp, const int* done) {
+  if (done && *done) return;
+  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (I > Nc || J > Nc) return;
+  restrict_node<0, T>(Nc, I, J, rfu, rcu, xcu);
+  restrict_node<1, T>(Nc, I, J, rfu, rcu, xcu);
+  restrict_node<2, T>(Nc, I, J, rfu, rcu, xcu);
+  restrict_node<3, T>(Nc, I, J, rfu, rcu, xcu);
+  const int Nf = 2 * Nc, NPf = Nf + 1;
+  auto Rp = [&](int i, int j) -> T {
+    return (i >= 0 && i <= Nf && j >= 0 && j <= Nf) ? rfp[(size_t)j * NPf + i] : T(0);
+  };
+  const int fi = 2 * I, fj = 2 * J;
+  const T v = Rp(fi, fj) + T(0.5) * (Rp(fi + 1, fj) + Rp(fi - 1, fj) + Rp(fi, fj + 1) +
+                                     Rp(fi, fj - 1) + Rp(fi + 1, fj + 1) + Rp(fi - 1, fj - 1));
+  rcp[(size_t)J * (Nc + 1) + I] = v;
+  if (xcp) xcp[(size_t)J * (Nc + 1) + I] = T(0);
+}
+
+template <class T>
+void launch_restrict(int Nc, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
+                     const int* done, hipStream_t s) {
+  dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
+  k_restrict<T><<<grid, 256, 0, s>>>(Nc, rfu, rfp, rcu, rcp, xcu, xcp, done);
+}
+template void launch_restrict<double>(int, const double*, const double*, double*, double*,
+                                      double*, double*, const int*, hipStream_t);
+template void launch_restrict<float>(int, const float*, const float*, float*, float*, float*,
+                                     float*, const int*, hipStream_t);
+
+template <int RA, int RB, class T, class FZ>
+__device__ __forceinline__ T pro_weights(FZ Z) {
+  if constexpr (RA == 0 && RB == 0) return SMG_PRO_00(Z);
+  else if constexpr (RA == 0 && RB == 1) return SMG_PRO_01(Z);
+  else if constexpr (RA == 0 && RB == 2) return SMG_PRO_02(Z);
+  else if constexpr (RA == 0 && RB == 3) return SMG_PRO_03(Z);
+  else if constexpr (RA == 1 && RB == 0) return SMG_PRO_10(Z);
+  else if constexpr (RA == 1 && RB == 1) return SMG_PRO_11(Z);
+  else if constexpr (RA == 1 && RB == 2) return SMG_PRO_12(Z);
+  else if constexpr (RA == 1 && RB == 3) return SMG_PRO_13(Z);
+  else if constexpr (RA == 2 && RB == 0) return SMG_PRO_20(Z);
+  else if constexpr (RA == 2 && RB == 1) return SMG_PRO_21(Z);
+  else if constexpr (RA == 2 && RB == 2) return SMG_PRO_22(Z);
+  else if constexpr (RA == 2 && RB == 3) return SMG_PRO_23(Z);
+  else if constexpr (RA == 3 && RB == 0) return SMG_PRO_30(Z);
+  else if constexpr (RA == 3 && RB == 1) return SMG_PRO_31(Z);
+  else if constexpr (RA == 3 && RB == 2) return SMG_PRO_32(Z);
+  else return SMG_PRO_33(Z);
+}
+
+template <int RA, int RB, class T, class FZ>
+__device__ __forceinline__ void pro_point(int Nf, int I, int J, FZ Z, T* uf) {
+  const int a = 4 * I + RA, b = 4 * J + RB;
+  if (a <= 0 || a >= 2 * Nf || b <= 0 || b >= 2 * Nf) return;
+  uf[(size_t)b * (2 * Nf + 1) + a] += pro_weights<RA, RB, T>(Z);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict__ zu,
+                                                     const T* __restrict__ zp, T* u, T* p,
+                                                     const int* done) {
+  if (done && *done) return;
+  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (I > Nc || J > Nc) return;
+  const int Nf = 2 * Nc, Mc = 2 * Nc + 1, Mf = 2 * Nf + 1;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const T* z = zu + (size_t)c * Mc * Mc;
+    T* uf = u + (size_t)c * Mf * Mf;
+    auto Z = [&](int dA, int dB) -> T {
+      const int A = 2 * I + dA, B = 2 * J + dB;
+      return (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc) ? z[(size_t)B * Mc + A] : T(0);
+    };
+    pro_point<0, 0, T>(Nf, I, J, Z, uf); pro_point<1, 0, T>(Nf, I, J, Z, uf);
+    pro_point<2, 0, T>(Nf, I, J, Z, uf); pro_point<3, 0, T>(Nf, I, J, Z, uf);
+    pro_point<0, 1, T>(Nf, I, J, Z, uf); pro_point<1, 1, T>(Nf, I, J, Z, uf);
+    pro_point<2, 1, T>(Nf, I, J, Z, uf); pro_point<3, 1, T>(Nf, I, J, Z, uf);
+    pro_point<0, 2, T>(Nf, I, J, Z, uf); pro_point<1, 2, T>(Nf, I, J, Z, uf);
+    pro_point<2, 2, T>(Nf, I, J, Z, uf); pro_point<3, 2, T>(Nf, I, J, Z, uf);
+    pro_point<0, 3, T>(Nf, I, J, Z, uf); pro_point<1, 3, T>(Nf, I, J, Z, uf);
+    pro_point<2, 3, T>(Nf, I, J, Z, uf); pro_point<3, 3, T>(Nf, I, J, Z, uf);
+  }
+  // P1: copy at coarse vertices, mean of the two ends at edge midpoints
+  const int NPc = Nc + 1, NPf = Nf + 1;
+  auto Zp = [&](int i, int j) -> T { return zp[(size_t)j * NPc + i]; };
+  const int fi = 2 * I, fj = 2 * J;
+  p[(size_t)fj * NPf + fi] += Zp(I, J);
+  if (I < Nc) p[(size_t)fj * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J));
+  if (J < Nc) p[(size_t)(fj + 1) * NPf + fi] += T(0.5) * (Zp(I, J) + Zp(I, J + 1));
+  if (I < Nc && J < Nc) p[(size_t)(fj + 1) * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J + 1));
+}
+
+template <class T>
+void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
+                        hipStream_t s) {
+  dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
+  k_prolong_add<T><<<grid, 256, 0, s>>>(Nc, zu, zp, u, p, done);
+}
+template void launch_prolong_add<double>(int, const double*, const double*, double*, double*,
+                                         const int*, hipStream_t);
+template void launch_prolong_add<float>(int, const float*, const float*, float*, float*,
+                                        const int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// coarsest grid: z = Cinv [r; 0] (Section 3, exact solve on level 0)
+// Compact order: velocity x then y at interior lattice points (b-major, then
+// a), then all pressure vertices, then the multiplier of m^T p = 0.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void k_coarse_solve(int N0, int nc, const double* __restrict__ cinv,
+                                                      const T* ru, const T* rp, T* zu, T* zp,
+                                                      const int* done) {
+  if (done && *done) return;
+  extern __shared__ double sh[];
+  double* sr = sh;
+  double* sz = sh + nc;
+  const int M0 = 2 * N0 + 1, ni = 2 * N0 - 1, nu = ni * ni, NP = N0 + 1;
+  for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+    double v = 0.0;
+    if (k < 2 * nu) {
+      const int c = k / nu, q = k % nu;
+      const int a = 1 + q % ni, b = 1 + q / ni;
+      v = (double)ru[(size_t)c * M0 * M0 + (size_t)b * M0 + a];
+    } else if (k < 2 * nu + NP * NP) {
+      v = (double)rp[k - 2 * nu];
+    }
+    sr[k] = v;
+  }
+  __syncthreads();
+  for (int row = threadIdx.x; row < nc; row += blockDim.x) {
+    double z = 0.0;
+    for (int j = 0; j < nc; ++j) z += cinv[(size_t)j * nc + row] * sr[j];
+    sz[row] = z;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * M0 * M0; k += blockDim.x) {
+    const int c = k / (M0 * M0), q = k % (M0 * M0);
+    const int a = q % M0, b = q / M0;
+    T v = T(0);
+    if (a > 0 && a < 2 * N0 && b > 0 && b < 2 * N0) v = (T)sz[c * nu + (b - 1) * ni + (a - 1)];
+    zu[k] = v;
+  }
+  for (int k = threadIdx.x; k < NP * NP; k += blockDim.x) zp[k] = (T)sz[2 * nu + k];
+}
+
+template <class T>
+void launch_coarse_solve(int N0, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
+                         T* zp, const int* done, hipStream_t s) {
+  k_coarse_solve<T><<<1, 256, 2 * nc * sizeof(double), s>>>(N0, nc, cinv, ru, rp, zu, zp, done);
+}
+template void launch_coarse_solve<double>(int, int, const double*, const double*, const double*,
+                                          double*, double*, const int*, hipStream_t);
+template void launch_coarse_solve<float>(int, int, const double*, const float*, const float*,
+                                         float*, float*, const int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// pressure mean: p <- p - (m . p) / sum m, m_i = int phi_i (relative weights:
+// 1 inside, 1/2 on edges, 1/3 at (0,0) and (1,1), 1/6 at (1,0) and (0,1))
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double p1_weight(int N, int i, int j) {
+  const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
+  if (!bi && !bj) return 1.0;
+  if (bi != bj) return 0.5;
+  return (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
+}
+
+constexpr int MEAN_PER_THREAD = 4;
+int mean_blocks(int N) {
+  const int n = (N + 1) * (N + 1);
+  return (n + 256 * MEAN_PER_THREAD - 1) / (256 * MEAN_PER_THREAD);
+}
+
+__global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __restrict__ p,
+                                                      double* partials, const int* done) {
+  if (done && *done) return;
+  __shared__ double red[4];
+  const int n = (N + 1) * (N + 1);
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < MEAN_PER_THREAD; ++k) {
+    const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
+    if (e < n) {
+      const double w = p1_weight(N, e % (N + 1), e / (N + 1));
+      s1 += w * p[e];
+      s2 += w;
+    }
+  }
+  const double t1 = block_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = block_sum<256>(s2, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = t1;
+    partials[2 * blockIdx.x + 1] = t2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mean_apply(int N, double* p, const double* __restrict__ partials,
+                                                    int nparts, const int* done) {
+  if (done && *done) return;
+  __shared__ double red[4];
+  __shared__ double mean;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    s1 += partials[2 * k];
+    s2 += partials[2 * k + 1];
+  }
+  const double t1 = block_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = block_sum<256>(s2, red);
+  if (threadIdx.x == 0) mean = t1 / t2;
+  __syncthreads();
+  const int n = (N + 1) * (N + 1);
+  for (int k = 0; k < MEAN_PER_THREAD; ++k) {
+    const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
+    if (e < n) p[e] -= mean;
+  }
+}
+
+void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s) {
+  const int nb = mean_blocks(N);
+  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, done);
+  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, done);
+}
+
+// ---------------------------------------------------------------------------
+// setup: Shat^-1 at every pressure vertex (Section 6: Shat = diag(B Ahat^-1 B^T),
+// the sum running over interior velocity nodes only)
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void k_shat_inv(int N, T ad0, T ad1, T ad2, T ad3, T* sinv) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1);
+  const T h = T(1) / T(N);
+  auto IN = [&](int da, int db) -> bool {
+    const int a = 2 * i + da, b = 2 * j + db;
+    return a > 0 && a < 2 * N && b > 0 && b < 2 * N;
+  };
+  auto AD = [&](int c) -> T { return c == 0 ? ad0 : c == 1 ? ad1 : c == 2 ? ad2 : ad3; };
+  const T S = h * h * SMG_SHAT_ROW(IN, AD);
+  sinv[e] = T(1) / S;
+}
+
+template <class T>
+void launch_shat_inv(int N, const T* ad, T* sinv, hipStream_t s) {
+  const int n = (N + 1) * (N + 1);
+  k_shat_inv<T><<<(n + 255) / 256, 256, 0, s>>>(N, ad[0], ad[1], ad[2], ad[3], sinv);
+}
+template void launch_shat_inv<double>(int, const double*, double*, hipStream_t);
+template void launch_shat_inv<float>(int, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// masses (load vectors and the adjoint): one thread per square, direct loads
+// ---------------------------------------------------------------------------
+
+template <int CLS>
+__device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int read_all,
+                                          const double* u, double* y) {
+  using T = double;
+  constexpr int DA = CLS & 1, DB = CLS >> 1;
+  const int M = 2 * N + 1;
+  const int a = 2 * i + DA, b = 2 * j + DB;
+  if (a > 2 * N || b > 2 * N) return;
+  const bool interior = a > 0 && a < 2 * N && b > 0 && b < 2 * N;
+  const double h2 = 1.0 / ((double)N * (double)N);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double* uc = u + (size_t)c * M * M;
+    auto U = [&](int da, int db) -> T {
+      const int aa = a + da, bb = b + db;
+      const bool ok = read_all ? (aa >= 0 && aa <= 2 * N && bb >= 0 && bb <= 2 * N)
+                               : (aa > 0 && aa < 2 * N && bb > 0 && bb < 2 * N);
+      return ok ? uc[(size_t)bb * M + aa] : 0.0;
+    };
+    const double v = (interior || rows_all) ? h2 * m_row<CLS, T>(U) : 0.0;
+    y[(size_t)c * M * M + (size_t)b * M + a] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mass_u(int N, int rows_all, int read_all,
+                                                const double* __restrict__ u, double* y) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1);
+  mass_node<0>(N, i, j, rows_all, read_all, u, y);
+  mass_node<1>(N, i, j, rows_all, read_all, u, y);
+  mass_node<2>(N, i, j, rows_all, read_all, u, y);
+  mass_node<3>(N, i, j, rows_all, read_all, u, y);
+}
+
+void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s) {
+  // mode 0: rows interior, read interior; 1: rows all, read interior; 2: rows interior, read all
+  const int n = (N + 1) * (N + 1);
+  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y);
+}
+
+// P1 mass: the six triangles around vertex (i, j) of the same-diagonal grid,
+// each of area h^2/2, contribute h^2/24 (2 g_i + g_a + g_b) when inside.
+__global__ __launch_bounds__(256) void k_mass_p(int N, const double* __restrict__ g, double* gp) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1), NP = N + 1;
+  auto G = [&](int ii, int jj) { return g[(size_t)jj * NP + ii]; };
+  auto sq = [&](int si, int sj) { return si >= 0 && si < N && sj >= 0 && sj < N; };
+  const double gi = G(i, j);
+  double s = 0.0;
+  if (sq(i - 1, j - 1)) {
+    s += 2 * gi + G(i - 1, j - 1) + G(i, j - 1);   // lower triangle of square (i-1, j-1)
+    s += 2 * gi + G(i - 1, j - 1) + G(i - 1, j);   // upper triangle
+  }
+  if (sq(i, j - 1)) s += 2 * gi + G(i, j - 1) + G(i + 1, j);      // upper triangle of (i, j-1)
+  if (sq(i - 1, j)) s += 2 * gi + G(i - 1, j) + G(i, j + 1);      // lower triangle of (i-1, j)
+  if (sq(i, j)) {
+    s += 2 * gi + G(i + 1, j) + G(i + 1, j + 1);   // lower triangle of (i, j)
+    s += 2 * gi + G(i + 1, j + 1) + G(i, j + 1);   // upper triangle
+  }
+  gp[e] = s / (24.0 * (double)N * (double)N);
+}
+
+void launch_mass_p(int N, const double* g, double* gp, hipStream_t s) {
+  const int n = (N + 1) * (N + 1);
+  k_mass_p<<<(n + 255) / 256, 256, 0, s>>>(N, g, gp);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic dots and the solve-loop bookkeeping
+// ---------------------------------------------------------------------------
+
+constexpr int DOT_PER_THREAD = 4;
+int dot_blocks(int N, int which) {
+  const int64_t n = which == 0 ? 2LL * (2 * N + 1) * (2 * N + 1) : (int64_t)(N + 1) * (N + 1);
+  return (int)((n + 256 * DOT_PER_THREAD - 1) / (256 * DOT_PER_THREAD));
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(int N, int which, const double* __restrict__ a,
+                                                     const double* __restrict__ b, double* partials) {
+  __shared__ double red[4];
+  const int M = 2 * N + 1;
+  const int64_t n = which == 0 ? 2LL * M * M : (int64_t)(N + 1) * (N + 1);
+  double s = 0.0;
+  for (int k = 0; k < DOT_PER_THREAD; ++k) {
+    const int64_t e = (int64_t)blockIdx.x * 256 * DOT_PER_THREAD + k * 256 + threadIdx.x;
+    if (e < n) {
+      bool ok = true;
+      if (which == 0) {
+        const int q = (int)(e % ((int64_t)M * M));
+        const int aa = q % M, bb = q / M;
+        ok = aa > 0 && aa < 2 * N && bb > 0 && bb < 2 * N;
+      }
+      if (ok) s += a[e] * b[e];
+    }
+  }
+  const double t = block_sum<256>(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int np,
+                                                      double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) s += partials[k];
+  const double t = block_sum<256>(s, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+void launch_reduce(const double* partials, int np, double* out, hipStream_t s) {
+  k_reduce_final<<<1, 256, 0, s>>>(partials, np, out);
+}
+
+void launch_dot(int N, int which, const double* a, const double* b, double* partials,
+                double* out, hipStream_t s) {
+  const int nb = dot_blocks(N, which);
+  k_dot_partial<<<nb, 256, 0, s>>>(N, which, a, b, partials);
+  k_reduce_final<<<1, 256, 0, s>>>(partials, nb, out);
+}
+
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partials, int np,
+                                               SolveState* st, double* hist) {
+  if (st->done) return;
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) s += partials[k];
+  const double r2 = block_sum<256>(s, red);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(r2 / st->fnorm2);
+    st->relres = rel;
+    const int it = st->iters + 1;
+    st->iters = it;
+    if (hist) hist[it - 1] = rel;
+    if (!(rel == rel) || rel > 1e300) st->done = 3;
+    else if (r2 <= st->tol2 * st->fnorm2) st->done = 1;
+    else if (rel > 1e6) st->done = 2;
+    else if (it >= st->maxit) st->done = 4;
+  }
+}
+
+void launch_check(const double* partials, int np, SolveState* st, double* hist, hipStream_t s) {
+  k_check<<<1, 256, 0, s>>>(partials, np, st, hist);
+}
+
+__global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ rpartials, int np,
+                                                    const double* __restrict__ fdots,
+                                                    SolveState* st) {
+  __shared__ double red[4];
+  double t = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) t += rpartials[k];
+  const double r2 = block_sum<256>(t, red);
+  if (threadIdx.x == 0) {
+    const double f2 = fdots[0] + fdots[1];
+    st->fnorm2 = f2;
+    st->iters = 0;
+    st->relres = f2 > 0 ? sqrt(r2 / f2) : 0.0;
+    st->done = (f2 == 0.0 || r2 <= st->tol2 * f2) ? 1 : 0;
+    if (!(r2 == r2) || !(f2 == f2)) st->done = 3;
+  }
+}
+
+void launch_init_state(const double* rpartials, int np, const double* fdots, SolveState* st,
+                       hipStream_t s) {
+  k_init_state<<<1, 256, 0, s>>>(rpartials, np, fdots, st);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(T* x, int64_t n, T v) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) x[e] = v;
+}
+void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  if (n > 0) k_fill<double><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
+}
+void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+  if (n > 0) k_fill<float><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
+}
+
+__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ a, float* b, int64_t n,
+                                              const int* done) {
+  if (done && *done) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) b[e] = (float)a[e];
+}
+void launch_cast_f64_f32(const double* a, float* b, int64_t n, const int* done, hipStream_t s) {
+  k_cast<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, b, n, done);
+}
+
+__global__ __launch_bounds__(256) void k_axpy_f32(double* x, const float* __restrict__ d, int64_t n,
+                                                  const int* done) {
+  if (done && *done) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) x[e] += (double)d[e];
+}
+void launch_axpy_f32(double* x, const float* d, int64_t n, const int* done, hipStream_t s) {
+  k_axpy_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, d, n, done);
+}
+
+}  // namespace smg

@@ -1,0 +1,221 @@
+"""Python front end of the MI355X coupled Stokes multigrid (thin: it checks
+shapes and marshals torch device pointers and the current stream into the C
+ABI of libstokesmg.so; all arithmetic runs in the HIP kernels).
+
+Layouts (level with N squares per side, M = 2N + 1), torch float64 on the GPU:
+    velocity   (2, M, M)      [component, y index, x index]
+    pressure   (N + 1, N + 1) [y index, x index]
+Pressure sign: the paper's variational form, i.e. minus the strong-form
+pressure of Section 1 (see include/stokesmg.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class SolveInfo:
+    status: str
+    iters: int
+    relres: float
+    history: list
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Hierarchy:
+    """A multigrid hierarchy of the generalized Stokes system on the unit square
+    (uniformly refined same-diagonal grid, Taylor-Hood P2-P1)."""
+
+    def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
+                 sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
+                 n0: int = 2, device=None):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP solver needs a GPU")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        if smoother not in _lib.SMOOTHERS:
+            raise ValueError(f"smoother must be one of {list(_lib.SMOOTHERS)}")
+        if tau is None:
+            tau = 0.35 if smoother == "ne" else 0.8
+        self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma),
+                                     int(nu_pre), int(nu_post), int(gamma), int(n0))
+        self.N, self.beta, self.smoother = int(N), float(beta), smoother
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.smg_setup(self.N, self.beta, C.byref(self.params), C.byref(h)),
+                       "smg_setup")
+        self.h = h
+        self.nlevels = self.lib.smg_num_levels(h)
+        self.L = self.nlevels - 1
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.smg_destroy(h)
+            self.h = None
+
+    # -- sizes / allocation ----------------------------------------------------
+    def level_N(self, level: int | None = None) -> int:
+        level = self.L if level is None else level
+        n = C.c_int()
+        _lib.check(self.lib.smg_level_size(self.h, level, C.byref(n), None, None), "smg_level_size")
+        return n.value
+
+    def shapes(self, level: int | None = None):
+        N = self.level_N(level)
+        return (2, 2 * N + 1, 2 * N + 1), (N + 1, N + 1)
+
+    def zeros(self, level: int | None = None, dtype=torch.float64):
+        su, sp = self.shapes(level)
+        return (torch.zeros(su, dtype=dtype, device=self.device),
+                torch.zeros(sp, dtype=dtype, device=self.device))
+
+    def dofs(self, level: int | None = None) -> int:
+        """Velocity (interior, both components) plus pressure (all nodes) unknowns."""
+        N = self.level_N(level)
+        return 2 * (2 * N - 1) ** 2 + (N + 1) ** 2
+
+    def _chk(self, level, *pairs, dtype=torch.float64):
+        su, sp = self.shapes(level)
+        for t, kind in pairs:
+            if t is None:
+                continue
+            shape = su if kind == "u" else sp
+            if t.dtype != dtype or t.device != self.device or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"expected contiguous {dtype} tensor of shape {shape} on {self.device}, "
+                                 f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+    # -- operators ---------------------------------------------------------------
+    def load(self, f_nodal, g_nodal, level=None):
+        level = self.L if level is None else level
+        self._chk(level, (f_nodal, "u"), (g_nodal, "p"))
+        fu, gp = self.zeros(level)
+        _lib.check(self.lib.smg_load(self.h, level, _ptr(f_nodal), _ptr(g_nodal), _ptr(fu), _ptr(gp),
+                                     _stream()), "smg_load")
+        return fu, gp
+
+    def mass(self, u, all_nodes=False, level=None):
+        level = self.L if level is None else level
+        self._chk(level, (u, "u"))
+        y = torch.empty_like(u)
+        _lib.check(self.lib.smg_mass(self.h, level, int(all_nodes), _ptr(u), _ptr(y), _stream()), "smg_mass")
+        return y
+
+    def pressure_mass(self, g, level=None):
+        level = self.L if level is None else level
+        self._chk(level, (g, "p"))
+        y = torch.empty_like(g)
+        _lib.check(self.lib.smg_pressure_mass(self.h, level, _ptr(g), _ptr(y), _stream()),
+                   "smg_pressure_mass")
+        return y
+
+    def apply(self, u, p, level=None):
+        level = self.L if level is None else level
+        self._chk(level, (u, "u"), (p, "p"))
+        yu, yp = torch.empty_like(u), torch.empty_like(p)
+        _lib.check(self.lib.smg_apply(self.h, level, _ptr(u), _ptr(p), _ptr(yu), _ptr(yp), _stream()),
+                   "smg_apply")
+        return yu, yp
+
+    def residual(self, fu, gp, u, p, level=None, norm=False):
+        level = self.L if level is None else level
+        self._chk(level, (fu, "u"), (gp, "p"), (u, "u"), (p, "p"))
+        ru, rp = torch.empty_like(u), torch.empty_like(p)
+        n2 = torch.zeros(1, dtype=torch.float64, device=self.device) if norm else None
+        _lib.check(self.lib.smg_residual(self.h, level, _ptr(fu), _ptr(gp), _ptr(u), _ptr(p), _ptr(ru),
+                                         _ptr(rp), _ptr(n2), _stream()), "smg_residual")
+        return (ru, rp, n2) if norm else (ru, rp)
+
+    def smooth(self, fu, gp, u, p, nsteps=1, level=None):
+        """In place on (u, p)."""
+        level = self.L if level is None else level
+        self._chk(level, (fu, "u"), (gp, "p"), (u, "u"), (p, "p"))
+        _lib.check(self.lib.smg_smooth(self.h, level, int(nsteps), _ptr(fu), _ptr(gp), _ptr(u), _ptr(p),
+                                       _stream()), "smg_smooth")
+        return u, p
+
+    def restrict(self, ru, rp, fine_level=None):
+        fine_level = self.L if fine_level is None else fine_level
+        self._chk(fine_level, (ru, "u"), (rp, "p"))
+        cu, cp = self.zeros(fine_level - 1)
+        _lib.check(self.lib.smg_restrict(self.h, fine_level, _ptr(ru), _ptr(rp), _ptr(cu), _ptr(cp),
+                                         _stream()), "smg_restrict")
+        return cu, cp
+
+    def prolong_add(self, zu, zp, u, p, fine_level=None):
+        """In place on (u, p)."""
+        fine_level = self.L if fine_level is None else fine_level
+        self._chk(fine_level - 1, (zu, "u"), (zp, "p"))
+        self._chk(fine_level, (u, "u"), (p, "p"))
+        _lib.check(self.lib.smg_prolong_add(self.h, fine_level, _ptr(zu), _ptr(zp), _ptr(u), _ptr(p),
+                                            _stream()), "smg_prolong_add")
+        return u, p
+
+    def coarse_solve(self, ru, rp):
+        self._chk(0, (ru, "u"), (rp, "p"))
+        zu, zp = self.zeros(0)
+        _lib.check(self.lib.smg_coarse_solve(self.h, _ptr(ru), _ptr(rp), _ptr(zu), _ptr(zp), _stream()),
+                   "smg_coarse_solve")
+        return zu, zp
+
+    def project_mean(self, p, level=None):
+        """In place on p."""
+        level = self.L if level is None else level
+        self._chk(level, (p, "p"))
+        _lib.check(self.lib.smg_project_mean(self.h, level, _ptr(p), _stream()), "smg_project_mean")
+        return p
+
+    def dot(self, a, b, which, level=None):
+        level = self.L if level is None else level
+        self._chk(level, (a, "u" if which == 0 else "p"), (b, "u" if which == 0 else "p"))
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.smg_dot(self.h, level, int(which), _ptr(a), _ptr(b), _ptr(out), _stream()),
+                   "smg_dot")
+        return out
+
+    # -- iterates ----------------------------------------------------------------
+    def cycle(self, fu, gp, u, p):
+        """One iterate on the finest level, in place on (u, p)."""
+        self._chk(self.L, (fu, "u"), (gp, "p"), (u, "u"), (p, "p"))
+        _lib.check(self.lib.smg_cycle(self.h, _ptr(fu), _ptr(gp), _ptr(u), _ptr(p), _stream()), "smg_cycle")
+        return u, p
+
+    def cycle_f32(self, fu, gp, u, p):
+        self._chk(self.L, (fu, "u"), (gp, "p"), (u, "u"), (p, "p"), dtype=torch.float32)
+        _lib.check(self.lib.smg_cycle_f32(self.h, _ptr(fu), _ptr(gp), _ptr(u), _ptr(p), _stream()),
+                   "smg_cycle_f32")
+        return u, p
+
+    def _solve(self, fn, name, fu, gp, rtol, maxit, u, p):
+        self._chk(self.L, (fu, "u"), (gp, "p"))
+        if u is None:
+            u, p = self.zeros()
+        self._chk(self.L, (u, "u"), (p, "p"))
+        it = C.c_int()
+        rel = C.c_double()
+        hist = (C.c_double * max(int(maxit), 1))()
+        code = fn(self.h, _ptr(fu), _ptr(gp), float(rtol), int(maxit), _ptr(u), _ptr(p), C.byref(it),
+                  C.byref(rel), hist, _stream())
+        _lib.check(code, name, soft_ok=True)
+        return u, p, SolveInfo(_lib.STATUS[code], it.value, rel.value, list(hist[: it.value]))
+
+    def solve(self, fu, gp, rtol=1e-8, maxit=200, u=None, p=None):
+        """Iterate to ||F - calA x|| <= rtol ||F||; returns (u, p, SolveInfo)."""
+        return self._solve(self.lib.smg_solve, "smg_solve", fu, gp, rtol, maxit, u, p)
+
+    def solve_mixed(self, fu, gp, rtol=1e-10, maxit=400, u=None, p=None):
+        """FP32 cycles inside FP64 iterative refinement."""
+        return self._solve(self.lib.smg_solve_mixed, "smg_solve_mixed", fu, gp, rtol, maxit, u, p)

@@ -1,0 +1,181 @@
+"""GPU parity of the multigrid iterate and of the solve loop against the oracle.
+
+The method is an iteration, so parity is checked iterate by iterate: after
+every top-level iterate the GPU and oracle (u, p) must agree to 1e-10
+relative (FP64 tolerance of the build), and a solve must stop after the same
+number of iterates (one more or fewer only if the residual lands within
+roundoff of the tolerance).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mixed as omixed
+from oracle import multigrid as mg
+from paper_1502_04070_amd import inputs
+from tests import lattice as lat
+from tests.test_gpu_ops import dev, gpu_hier, host, oracle_level
+
+pytestmark = pytest.mark.gpu
+PARITY = 1e-10
+
+
+def _rhs(gh, oh, F, G):
+    """Load vectors on both sides from the same nodal data (g made mean-free by the oracle's m)."""
+    d = oh.discs[-1]
+    fn, gn = lat.lattice_to_nodal(d, F, G)
+    gn = gn - (oh.top.m @ gn) / oh.top.m.sum()
+    fu, gp = d.load(fn, gn)
+    f = np.concatenate([fu, gp])
+    FU, GP = lat.to_lattice(d, f)
+    return f, dev(FU), dev(GP)
+
+
+def _params(kind):
+    return {"ne": (dict(smoother="ne"), mg.Params()),
+            "uzawa": (dict(smoother="uzawa", nu_pre=3, nu_post=3), mg.Params.uzawa()),
+            "ne_w": (dict(smoother="ne", gamma=2), mg.Params("ne", 0.35, 0.8, 2, 2, 2)),
+            "uzawa_w": (dict(smoother="uzawa", nu_pre=3, nu_post=3, gamma=2), mg.Params.uzawa(gamma=2)),
+            "ne_11": (dict(smoother="ne", nu_pre=1, nu_post=1), mg.Params("ne", 0.35, 0.8, 1, 1, 1)),
+            "ne_0pre": (dict(smoother="ne", nu_pre=0, nu_post=2), mg.Params("ne", 0.35, 0.8, 0, 2, 1))}[kind]
+
+
+@pytest.mark.parametrize("kind", ["ne", "uzawa", "ne_w", "uzawa_w", "ne_11", "ne_0pre"])
+@pytest.mark.parametrize("N,n0,beta", [(8, 4, 1.0), (32, 2, 0.0), (32, 2, 1e4), (48, 3, 1e6)])
+def test_iterates_match_oracle(kind, N, n0, beta):
+    print(f"cycle {kind} N={N} n0={n0} beta={beta}", flush=True)
+    gkw, prm = _params(kind)
+    oh = oracle_level(N, beta, n0)
+    gh = gpu_hier(N, beta, n0=n0, **gkw)
+    F, G = inputs.normal_fg(N, seed=21)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    d = oh.discs[-1]
+    x = np.zeros(oh.top.n)
+    U, P = gh.zeros()
+    for it in range(4):
+        gh.cycle(FU, GP, U, P)
+        x = mg.top_cycle(oh, x, f, prm)
+        got = lat.from_lattice(d, host(U), host(P))
+        err = np.linalg.norm(got - x) / np.linalg.norm(x)
+        assert err <= PARITY, (it, err)
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 1e2, 1e4, 1e6])
+def test_solve_full_size_matches_oracle(beta):
+    """N = 128 (66049 P2 nodes per component, 16641 P1 nodes), f iid U[-1,1]
+    (seed 0), g = 0, NE V(2,2) to 1e-8: same iterate count, same solution."""
+    N = 128
+    print(f"solve N={N} beta={beta}", flush=True)
+    oh = oracle_level(N, beta, 2)
+    gh = gpu_hier(N, beta)
+    F, G = inputs.uniform_f(N, seed=0)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    res = mg.solve(oh, f, mg.Params(), tol=1e-8, maxit=300)
+    U, P, info = gh.solve(FU, GP, rtol=1e-8, maxit=300)
+    assert info.status == "ok"
+    near = abs(res.relres - 1e-8) < 1e-3 * 1e-8
+    assert info.iters == res.iters or (near and abs(info.iters - res.iters) == 1), (info.iters, res.iters)
+    got = lat.from_lattice(oh.discs[-1], host(U), host(P))
+    assert np.linalg.norm(got - res.x) <= PARITY * np.linalg.norm(res.x)
+    assert np.allclose(info.history, res.history, rtol=1e-8, atol=0)
+
+
+def test_two_grid_config_solve():
+    """N = 8 with the exact solve on N = 4 (two grids), beta = 1, f iid U[-1,1]
+    (seed 0), g = 0, NE V(2,2), tol 1e-8."""
+    oh = oracle_level(8, 1.0, 4)
+    gh = gpu_hier(8, 1.0, n0=4)
+    F, G = inputs.uniform_f(8, seed=0)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    res = mg.solve(oh, f, mg.Params(), tol=1e-8)
+    U, P, info = gh.solve(FU, GP, rtol=1e-8)
+    assert info.iters == res.iters
+    got = lat.from_lattice(oh.discs[-1], host(U), host(P))
+    assert np.linalg.norm(got - res.x) <= PARITY * np.linalg.norm(res.x)
+    xd = oh.top.project_mean(oh.top.direct_solve(f))
+    assert np.linalg.norm(got - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
+def test_solve_edge_cases():
+    gh = gpu_hier(16, 1.0)
+    U0, P0 = gh.zeros()
+    # zero right-hand side: zero iterates, zero solution
+    U, P, info = gh.solve(U0.clone(), P0.clone(), rtol=1e-8)
+    assert info.status == "ok" and info.iters == 0 and float(U.abs().max()) == 0.0
+    # maxit reached: soft status, last iterate returned
+    F, G = inputs.uniform_f(16, seed=1)
+    FU = dev(F)
+    gh.zeros()
+    U, P, info = gh.solve(FU, P0.clone(), rtol=1e-14, maxit=3)
+    assert info.status == "noconv" and info.iters == 3
+    # the finest level equal to the coarsest: one exact solve
+    g0 = gpu_hier(4, 2.0, n0=4)
+    oh = oracle_level(4, 2.0, 4)
+    F4, G4 = inputs.uniform_f(4, seed=2)
+    f, FU4, GP4 = _rhs(g0, oh, F4, G4)
+    U, P, info = g0.solve(FU4, GP4, rtol=1e-12)
+    assert info.iters == 1
+    xd = oh.top.project_mean(oh.top.direct_solve(f))
+    got = lat.from_lattice(oh.discs[-1], host(U), host(P))
+    assert np.linalg.norm(got - xd) <= 1e-11 * np.linalg.norm(xd)
+    # a non-finite right-hand side is reported, not hidden
+    FU[0, 3, 3] = float("nan")
+    U, P, info = gh.solve(FU, P0.clone(), rtol=1e-8)
+    assert info.status == "nonfinite"
+
+
+def test_initial_guess_boundary_ignored_and_restart():
+    """Checkpoint / resume: restarting from a saved iterate continues the same sequence."""
+    N = 32
+    oh = oracle_level(N, 5.0, 2)
+    gh = gpu_hier(N, 5.0)
+    F, G = inputs.normal_fg(N, seed=30)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    U, P, i1 = gh.solve(FU, GP, rtol=1e-4)
+    U2 = U.clone()
+    U2[:, 0, :] = 3.0                      # junk on the boundary of the guess
+    U2, P2, i2 = gh.solve(FU, GP, rtol=1e-9, u=U2, p=P.clone())
+    U3, P3, i3 = gh.solve(FU, GP, rtol=1e-9)
+    assert i2.status == "ok" and i3.status == "ok"
+    assert i1.iters + i2.iters in (i3.iters, i3.iters + 1)
+    assert float(U2[:, 0, :].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("beta", [1.0, 1e4])
+def test_fp32_cycle_matches_oracle_fp32_cycle(beta):
+    N = 64
+    oh = oracle_level(N, beta, 2)
+    gh = gpu_hier(N, beta)
+    F, G = inputs.normal_fg(N, seed=40)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    d = oh.discs[-1]
+    x0 = oh.top.project_mean(np.random.default_rng(3).standard_normal(oh.top.n))
+    u0, p0 = lat.to_lattice(d, x0)
+    U = dev(u0).float()
+    P = dev(p0).float()
+    gh.cycle_f32(FU.float(), GP.float(), U, P)
+    h32 = omixed._Hierarchy32(oh)
+    x32 = mg.cycle(h32, oh.L, x0.astype(np.float32), f.astype(np.float32), mg.Params()).astype(np.float64)
+    got = lat.from_lattice(d, host(U).astype(np.float64), host(P).astype(np.float64))
+    lv = oh.top
+    diff = lv.project_mean(got) - lv.project_mean(x32)
+    assert np.linalg.norm(diff) <= 1e-5 * np.linalg.norm(lv.project_mean(x32) - x0)
+
+
+@pytest.mark.parametrize("beta", [1.0, 1e4])
+def test_mixed_precision_solve_reaches_fp64_accuracy(beta):
+    N = 64
+    oh = oracle_level(N, beta, 2)
+    gh = gpu_hier(N, beta)
+    F, G = inputs.smooth_plus_noise(N, seed=0)
+    f, FU, GP = _rhs(gh, oh, F, G)
+    U, P, info = gh.solve_mixed(FU, GP, rtol=1e-10, maxit=400)
+    assert info.status == "ok" and info.relres <= 1e-10
+    got = lat.from_lattice(oh.discs[-1], host(U), host(P))
+    r = f - oh.top.calA @ got
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f)
+    xd = oh.top.project_mean(oh.top.direct_solve(f))
+    assert np.linalg.norm(got - xd) <= 1e-7 * np.linalg.norm(xd)
+    # the FP64 solve takes about as many cycles (a linear iterate is the same in both forms)
+    _, _, i64 = gh.solve(FU, GP, rtol=1e-10, maxit=400)
+    assert abs(i64.iters - info.iters) <= max(3, 0.1 * i64.iters)
