@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: coupled multigrid solves of the generalized Stokes system on one MI355X.
+
+Workload (one "step"): the unit square, same-diagonal grid refined to h = 1/128
+(66049 P2 nodes per velocity component, 16641 P1 pressure nodes; 146691
+unknowns), Taylor-Hood P2-P1, f = P2 nodal values iid uniform[-1, 1] (seed 0),
+g = 0, solved to 1e-8 relative residual with the FP64 normal-equation V(2,2)
+cycle (7 levels, coarsest h = 1/2) for each beta in {0, 1, 1e2, 1e4, 1e6}.
+Inputs are synthetic and resident in HBM before the timed region.
+
+Metric: velocity + pressure unknowns x multigrid cycles per second, summed
+over the five solves; time to 1e-8 per beta is reported beside it, for the
+FP64 solver and for FP32 cycles inside FP64 iterative refinement.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_GRID = 128
+BETAS = [0.0, 1.0, 1e2, 1e4, 1e6]
+TOL = 1e-8
+HBM_PEAK_GBS = 8000.0
+
+
+def dofs(N):
+    return 2 * (2 * N - 1) ** 2 + (N + 1) ** 2
+
+
+def ne_pass1_bytes(N):
+    """Algorithmic HBM bytes of one finest-level normal-equation pass 1
+    (t = L^-1 (F - calA x)): read x and F (all unknowns), read Shat^-1 (one
+    per pressure node), write t (all unknowns); 8-byte words, each once."""
+    n, npres = dofs(N), (N + 1) ** 2
+    return 8 * (3 * n + npres)
+
+
+def cpu_baseline(n_cycles=30):
+    """The oracle (SciPy CSR, FP64) on a bounded sample of the same workload:
+    `n_cycles` V(2,2) iterates plus residual norms for each beta at h = 1/128."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import numpy as np
+    from oracle import multigrid as mg
+    from paper_1502_04070_amd import inputs
+    from tests import lattice as lat
+
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        total_dof_cycles = 0
+        t_total = 0.0
+        for beta in BETAS:
+            h = mg.Hierarchy("same_diag", 6, beta, n0=2)
+            d = h.discs[-1]
+            F, G = inputs.uniform_f(N_GRID, seed=0)
+            fn, gn = lat.lattice_to_nodal(d, F, G)
+            f = np.concatenate(d.load(fn, gn))
+            x = np.zeros(h.top.n)
+            t0 = time.perf_counter()
+            for _ in range(n_cycles):
+                x = mg.top_cycle(h, x, f, mg.Params())
+                np.linalg.norm(mg.residual(h.top, x, f))
+            t_total += time.perf_counter() - t0
+            total_dof_cycles += dofs(N_GRID) * n_cycles
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"value": total_dof_cycles / t_total, "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cycles} NE V(2,2) iterates + residual norm per beta in {BETAS} at h=1/128 "
+                      f"({len(BETAS) * n_cycles} cycles, {t_total:.1f} s, 1 thread, setup excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    F, G = inputs.uniform_f(N_GRID, seed=0)
+    Fd = torch.from_numpy(F).cuda()
+    Gd = torch.from_numpy(G).cuda()
+    hs = [Hierarchy(N_GRID, b) for b in BETAS]
+    loads = [h.load(Fd, Gd) for h in hs]            # resident load vectors
+    outs = [h.zeros() for h in hs]
+    torch.cuda.synchronize()
+
+    def step(mixed=False):
+        its, per = [], []
+        for h, (fu, gp), (u, p) in zip(hs, loads, outs):
+            u.zero_()
+            p.zero_()
+            t0 = time.perf_counter()
+            if mixed:
+                _, _, info = h.solve_mixed(fu, gp, rtol=TOL, maxit=500, u=u, p=p)
+            else:
+                _, _, info = h.solve(fu, gp, rtol=TOL, maxit=500, u=u, p=p)
+            per.append(time.perf_counter() - t0)
+            assert info.status == "ok", info
+            its.append(info.iters)
+        return its, per
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_its, per_beta = [], [0.0] * len(BETAS)
+    for _ in range(args.steps):
+        its, per = step()
+        all_its.append(its)
+        per_beta = [a + b for a, b in zip(per_beta, per)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cycles = sum(sum(x) for x in all_its)
+    value = dofs(N_GRID) * cycles / elapsed
+    iters = all_its[-1]
+
+    # FP32 cycles inside FP64 refinement on the same workload
+    step(mixed=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mixed_its, mixed_per = step(mixed=True)
+    torch.cuda.synchronize()
+    mixed_elapsed = time.perf_counter() - t1
+
+    # dominant kernel: the finest-level normal-equation pass 1, timed with HIP
+    # events on the stream it runs on
+    kern_ms = hs[1].time_kernel(0, reps=args.kernel_reps)
+    kbytes = ne_pass1_bytes(N_GRID)
+    achieved = kbytes / (kern_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "velocity+pressure DOF*cycles/s (FP64 NE V(2,2) to 1e-8, h=1/128, 5 betas)",
+        "value": value,
+        "unit": "DOF*cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "generalized Stokes, unit square, h=1/128 same-diagonal grid, Taylor-Hood "
+                               "P2-P1, f iid U[-1,1] (seed 0), g=0, FP64 NE V(2,2) to 1e-8, beta in "
+                               "{0,1,1e2,1e4,1e6}",
+                   "N": N_GRID, "dof": dofs(N_GRID), "betas": BETAS, "levels": hs[0].nlevels},
+        "iterations": dict(zip([str(b) for b in BETAS], iters)),
+        "time_to_tol_ms": dict(zip([str(b) for b in BETAS], [1e3 * t / args.steps for t in per_beta])),
+        "fp32_refine": {
+            "value": dofs(N_GRID) * sum(mixed_its) / mixed_elapsed,
+            "iterations": dict(zip([str(b) for b in BETAS], mixed_its)),
+            "time_to_tol_ms": dict(zip([str(b) for b in BETAS], [1e3 * t for t in mixed_per])),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "finest-level normal-equation pass 1 (k_stencil, M_NE1)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": kbytes,
+            "avg_launch_us": kern_ms * 1e3,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

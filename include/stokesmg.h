@@ -78,9 +78,13 @@ typedef struct {
   int nu_post;    /* smoothing steps after it                                   */
   int gamma;      /* 1 = V-cycle, 2 = W-cycle                                    */
   int n0;         /* cells per side of the coarsest grid (>= 2); solved exactly */
+  int unfused;    /* 0 (default): fused kernels (one launch per smoothing step,
+                     defect + restriction in one launch, the levels with at most
+                     16 squares per side in one single-workgroup launch);
+                     1: one launch per operator application (reference path) */
 } smg_params;
 
-/* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2. */
+/* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2, fused. */
 int smg_default_params(smg_params* prm);
 
 /* Thread-local description of the last error (never NULL). */
@@ -203,6 +207,17 @@ int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
  */
 int smg_dot(smg_t h, int level, int which, const double* a, const double* b, double* out,
             smg_stream_t s);
+
+/*
+ * Kernel timing (profiling support): launches `reps` times, back to back on
+ * stream s, one kernel of the finest level on the handle's internal work
+ * vectors and returns the mean duration in milliseconds measured with HIP
+ * events recorded on s.  which: 0 = normal-equation pass 1 (t = L^-1 (F -
+ * calA x)), 1 = normal-equation pass 2 (x += tau L^-1 calA t), 2 = residual
+ * (t = F - calA x), 3 = operator (t = calA x).  The work vectors' contents
+ * are overwritten.  Synchronous.
+ */
+int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t s);
 
 #ifdef __cplusplus
 }

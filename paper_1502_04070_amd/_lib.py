@@ -19,7 +19,8 @@ SMOOTHERS = {"ne": 0, "uzawa": 1}
 
 class SmgParams(C.Structure):
     _fields_ = [("smoother", C.c_int), ("tau", C.c_double), ("sigma", C.c_double),
-                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("gamma", C.c_int), ("n0", C.c_int)]
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("gamma", C.c_int), ("n0", C.c_int),
+                ("unfused", C.c_int)]
 
 
 class SmgError(RuntimeError):
@@ -53,6 +54,7 @@ SIGNATURES = {
     "smg_solve": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],
     "smg_solve_mixed": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],
     "smg_dot": [P, I, I, P, P, P, P],
+    "smg_time_kernel": [P, I, I, C.POINTER(D), P],
 }
 
 _lib = None

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstokesmg.so")
-SOURCES = ["smg_kernels.hip", "smg_capi.hip"]
+SOURCES = ["smg_kernels.hip", "smg_fused.hip", "smg_capi.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "smg_fused.h"
 #include "smg_internal.h"
 #include "stokesmg.h"
 
@@ -100,6 +101,12 @@ struct smg_hier {
   double* fdots = nullptr;         // 2 doubles
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
+  // single-workgroup iterate of levels 0..Lc (Lc = -1: not used)
+  int Lc = -1;
+  int* cc_ops = nullptr;
+  int cc_nops = 0;
+  double* mpart = nullptr;         // pressure-mean partials of the finest level
+  bool fused = true;
   std::vector<void*> allocs;
 
   template <class T>
@@ -359,6 +366,155 @@ void cycle_rec(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done,
   for (int k = 0; k < prm.nu_post; ++k) smooth_step<T>(prm, L, x, f, t, false, done, s);
 }
 
+// ---------------------------------------------------------------------------
+// fused iterate: k_ne steps alternating between the level's x and t buffers,
+// k_resid_restrict, and one k_coarse_cycle launch for levels 0..Lc
+// ---------------------------------------------------------------------------
+
+// op list of the single-workgroup kernel, the recursion of Section 3 on
+// levels l..0 written out (zg: the iterate of level l is zero on entry)
+void cc_emit(const smg_params& prm, int l, bool zg, std::vector<int>& ops) {
+  if (l == 0) {
+    ops.push_back(cc_op(CC_COARSE, 0, 0));
+    return;
+  }
+  const int sm = prm.smoother == SMG_SMOOTHER_NE ? CC_NE : CC_UZAWA;
+  bool z = zg;
+  for (int k = 0; k < prm.nu_pre; ++k) {
+    ops.push_back(cc_op(sm, l, z ? 1 : 0));
+    z = false;
+  }
+  ops.push_back(cc_op(CC_RESTRICT, l, 0));     // also zeroes the coarse iterate
+  for (int g = 0; g < prm.gamma; ++g) cc_emit(prm, l - 1, g == 0, ops);
+  ops.push_back(cc_op(CC_PROLONG, l, 0));
+  for (int k = 0; k < prm.nu_post; ++k) ops.push_back(cc_op(sm, l, 0));
+}
+
+template <class T>
+void coarse_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+  CoarseJob<T> J{};
+  for (int l = 0; l <= H->Lc; ++l) J.L[l] = Sel<T>::c(H->lv[l]);
+  J.n0 = H->prm.n0;
+  J.Lc = H->Lc;
+  J.nc = H->nc;
+  J.nops = H->cc_nops;
+  J.ops = H->cc_ops;
+  J.cinv = H->cinv;
+  J.fu = f.u; J.fp = f.p;
+  J.xu = x.u; J.xp = x.p;
+  J.zero_guess = zg ? 1 : 0;
+  J.tau = T(H->prm.tau);
+  J.sigma = T(H->prm.sigma);
+  J.done = done;
+  launch_coarse_cycle<T>(J, s);
+}
+
+template <class T>
+void copy_vec(Level& L, Vec<T> dst, Vec<T> src, const int* done, hipStream_t s) {
+  StencilJob<T> C = job_of<T>(L);
+  C.rhs_u = src.u; C.rhs_p = src.p;
+  C.out_u = dst.u; C.out_p = dst.p;
+  C.done = done;
+  launch_stencil<T>(C, ROWS_UP, s);   // dst = 0 + 1 * (src - 0), boundary written 0
+}
+
+// Fused iterate on level l for (x, f).  Returns the buffer holding the
+// result: x itself, or the level's t buffer (its ping-pong partner).
+template <class T>
+Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+  if (l <= H->Lc) {
+    coarse_cycle<T>(H, x, f, zg, done, s);
+    return x;
+  }
+  Level& L = H->lv[l];
+  const smg_params& prm = H->prm;
+  const bool ne = prm.smoother == SMG_SMOOTHER_NE;
+  // ping-pong partner: whichever of the level's two buffers does not hold x
+  Vec<T> cur = x, alt = (x.u == Sel<T>::t(L).u) ? Sel<T>::x(L) : Sel<T>::t(L);
+  bool z = zg;
+  if (z && prm.nu_pre == 0) {
+    fill_vec<T>(L, cur, s);
+    z = false;
+  }
+  for (int k = 0; k < prm.nu_pre; ++k) {
+    if (ne) {
+      NEJob<T> J{};
+      J.L = Sel<T>::c(L);
+      J.xu = cur.u; J.xp = cur.p;
+      J.fu = f.u; J.fp = f.p;
+      J.ou = alt.u; J.op = alt.p;
+      J.tau = T(prm.tau);
+      J.done = done;
+      launch_ne<T>(J, z, false, s);
+      std::swap(cur, alt);
+    } else {
+      // Uzawa: three passes through the level's t buffer, result in place
+      // (t is free here: the iterate stays in cur)
+      smooth_step<T>(prm, L, cur, f, alt, z, done, s);
+    }
+    z = false;
+  }
+  Level& C = H->lv[l - 1];
+  Vec<T> xc = Sel<T>::x(C), fc = Sel<T>::f(C);
+  {
+    RRJob<T> R{};
+    R.L = Sel<T>::c(L);
+    R.xu = cur.u; R.xp = cur.p;
+    R.fu = f.u; R.fp = f.p;
+    R.cu = fc.u; R.cp = fc.p;
+    R.done = done;
+    launch_resid_restrict<T>(R, s);
+  }
+  Vec<T> zc = xc;
+  for (int g = 0; g < prm.gamma; ++g) {
+    zc = cycle_fused<T>(H, l - 1, zc, fc, g == 0, done, s);
+  }
+  int post = prm.nu_post;
+  if (ne && post > 0) {
+    NEJob<T> J{};
+    J.L = Sel<T>::c(L);
+    J.xu = cur.u; J.xp = cur.p;
+    J.fu = f.u; J.fp = f.p;
+    J.ou = alt.u; J.op = alt.p;
+    J.zu = zc.u; J.zp = zc.p;
+    J.tau = T(prm.tau);
+    J.done = done;
+    launch_ne<T>(J, false, true, s);
+    std::swap(cur, alt);
+    --post;
+  } else {
+    launch_prolong_add<T>(C.N, zc.u, zc.p, cur.u, cur.p, done, s);
+  }
+  for (int k = 0; k < post; ++k) {
+    if (ne) {
+      NEJob<T> J{};
+      J.L = Sel<T>::c(L);
+      J.xu = cur.u; J.xp = cur.p;
+      J.fu = f.u; J.fp = f.p;
+      J.ou = alt.u; J.op = alt.p;
+      J.tau = T(prm.tau);
+      J.done = done;
+      launch_ne<T>(J, false, false, s);
+      std::swap(cur, alt);
+    } else {
+      smooth_step<T>(prm, L, cur, f, alt, false, done, s);
+    }
+  }
+  return cur;
+}
+
+// iterate on the finest level with the result in x
+template <class T>
+void top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+  if (!H->fused) {
+    if (zg) fill_vec<T>(H->lv[H->L], x, s);
+    cycle_rec<T>(H, H->L, x, f, false, done, s);
+    return;
+  }
+  Vec<T> r = cycle_fused<T>(H, H->L, x, f, zg, done, s);
+  if (r.u != x.u) copy_vec<T>(H->lv[H->L], x, r, done, s);
+}
+
 void project_mean(smg_hier* H, int l, double* p, const int* done, hipStream_t s) {
   launch_project_mean(H->lv[l].N, p, H->red, done, s);
 }
@@ -375,26 +531,38 @@ void top_residual(Level& L, const double* xu, const double* xp, const double* fu
   launch_stencil<double>(R, ROWS_UP, s);
 }
 
+// end of an iterate: residual norm and pressure-mean pieces of x in one pass,
+// mean projection, convergence test (the residual is blind to the mean)
+void finish_iter(smg_hier* H, double* ru, double* rp, const int* done, hipStream_t s) {
+  Level& T = H->lv[H->L];
+  StencilJob<double> R = job_of<double>(T);
+  R.in_u = T.x.u; R.in_p = T.x.p;
+  R.rhs_u = T.f.u; R.rhs_p = T.f.p;
+  R.out_u = ru; R.out_p = rp;
+  R.partial = T.partial;
+  R.mean_partial = H->mpart;
+  R.done = done;
+  launch_stencil<double>(R, ROWS_UP, s);
+  launch_project_partials(H->mpart, T.ntiles, T.N, T.x.p, done, s);
+  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+}
+
 // one FP64 iterate of the solve loop on the internal finest-level vectors
 void enqueue_iter64(smg_hier* H, hipStream_t s) {
   Level& T = H->lv[H->L];
   const int* done = &H->st->done;
-  cycle_rec<double>(H, H->L, T.x, T.f, false, done, s);
-  project_mean(H, H->L, T.x.p, done, s);
-  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, nullptr, nullptr, done, s);
-  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+  top_cycle<double>(H, T.x, T.f, false, done, s);
+  finish_iter(H, nullptr, nullptr, done, s);
 }
 
-// one refinement step: d = cycle_fp32(r), x += d, project, r = F - calA x
+// one refinement step: d = cycle_fp32(r), x += d, r = F - calA x, project, test
 void enqueue_iter_mixed(smg_hier* H, hipStream_t s) {
   Level& T = H->lv[H->L];
   const int* done = &H->st->done;
   launch_cast_f64_f32(T.t.u, T.f32.u, T.n_u + T.n_p, done, s);
-  cycle_rec<float>(H, H->L, T.x32, T.f32, true, done, s);
+  top_cycle<float>(H, T.x32, T.f32, true, done, s);
   launch_axpy_f32(T.x.u, T.x32.u, T.n_u + T.n_p, done, s);
-  project_mean(H, H->L, T.x.p, done, s);
-  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, T.t.u, T.t.p, done, s);
-  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+  finish_iter(H, T.t.u, T.t.p, done, s);
 }
 
 int capture(smg_hier* H, void (*fn)(smg_hier*, hipStream_t), hipGraphExec_t* out) {
@@ -518,6 +686,7 @@ int smg_default_params(smg_params* prm) {
   prm->nu_post = 2;
   prm->gamma = 1;
   prm->n0 = 2;
+  prm->unfused = 0;
   return SMG_OK;
 }
 
@@ -547,6 +716,7 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   smg_hier* H = new smg_hier();
   H->prm = prm;
   H->beta = beta;
+  H->fused = prm.unfused == 0;
   H->L = L;
   if (hipGetDevice(&H->device) != hipSuccess) { delete H; return fail(SMG_EHIP, "hipGetDevice"); }
   H->lv.resize(L + 1);
@@ -616,6 +786,39 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
       hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
     delete H;
     return fail(SMG_EHIP, "setup upload / kernels failed");
+  }
+  // levels handled by the single-workgroup kernel: N <= 16 and all three
+  // vectors of every such level in FP64 within the LDS of one workgroup
+  {
+    int lds_max = 0, lds_optin = 0;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device);
+    (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, H->device);
+    const size_t limit = (size_t)std::max(lds_max, lds_optin);
+    H->Lc = -1;
+    for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
+      if ((prm.n0 << l) > 16) break;
+      const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));
+      if (need > limit) break;
+      if (need > 65536 && (coarse_cycle_allow_lds<double>(need) != 0 ||
+                           coarse_cycle_allow_lds<float>(coarse_cycle_lds(prm.n0, l, sizeof(float))) != 0)) {
+        (void)hipGetLastError();
+        break;
+      }
+      H->Lc = l;
+    }
+    if (H->Lc >= 0) {
+      std::vector<int> ops;
+      cc_emit(prm, H->Lc, true, ops);
+      H->cc_nops = (int)ops.size();
+      H->cc_ops = H->alloc<int>(H->cc_nops);
+      if (!H->cc_ops) { delete H; return fail(SMG_ENOMEM, "op list"); }
+      if (hipMemcpy(H->cc_ops, ops.data(), ops.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        delete H;
+        return fail(SMG_EHIP, "op list upload");
+      }
+    }
+    H->mpart = H->alloc<double>(2 * H->lv[L].ntiles);
+    if (!H->mpart) { delete H; return fail(SMG_ENOMEM, "mean partials"); }
   }
   *out = H;
   return SMG_OK;
@@ -755,7 +958,7 @@ int smg_cycle(smg_t h, const double* fu, const double* gp, double* u, double* p,
   if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)sv;
   Vec<double> x{u, p}, f{const_cast<double*>(fu), const_cast<double*>(gp)};
-  cycle_rec<double>(h, h->L, x, f, false, nullptr, s);
+  top_cycle<double>(h, x, f, false, nullptr, s);
   project_mean(h, h->L, p, nullptr, s);
   return launch_status("smg_cycle");
 }
@@ -765,7 +968,7 @@ int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
   if (rc) return rc;
   if (!fu || !gp || !u || !p) return fail(SMG_EINVAL, "null vector");
   Vec<float> x{u, p}, f{const_cast<float*>(fu), const_cast<float*>(gp)};
-  cycle_rec<float>(h, h->L, x, f, false, nullptr, (hipStream_t)sv);
+  top_cycle<float>(h, x, f, false, nullptr, (hipStream_t)sv);
   return launch_status("smg_cycle_f32");
 }
 
@@ -790,6 +993,41 @@ int smg_dot(smg_t h, int level, int which, const double* a, const double* b, dou
   if (which != 0 && which != 1) return fail(SMG_EINVAL, "which must be 0 or 1");
   launch_dot(h->lv[level].N, which, a, b, h->red, out, (hipStream_t)sv);
   return launch_status("smg_dot");
+}
+
+int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t sv) {
+  int rc = check_level(h, 0);
+  if (rc) return rc;
+  if (!avg_ms || reps < 1 || which < 0 || which > 3) return fail(SMG_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)sv;
+  Level& T = h->lv[h->L];
+  StencilJob<double> J = job_of<double>(T);
+  J.in_u = T.x.u; J.in_p = T.x.p;
+  J.out_u = T.t.u; J.out_p = T.t.p;
+  if (which == 0 || which == 2) { J.rhs_u = T.f.u; J.rhs_p = T.f.p; }
+  if (which == 0) J.diag_u = J.diag_p = 1;
+  if (which == 1) {
+    J.in_u = T.t.u; J.in_p = T.t.p;
+    J.base_u = T.x.u; J.base_p = T.x.p;
+    J.out_u = T.x.u; J.out_p = T.x.p;
+    J.w_u = J.w_p = -h->prm.tau;
+    J.diag_u = J.diag_p = 1;
+  }
+  if (which == 3) J.w_u = J.w_p = -1.0;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  launch_stencil<double>(J, ROWS_UP, s);  // warm-up
+  HIPCHK(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) launch_stencil<double>(J, ROWS_UP, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return launch_status("smg_time_kernel");
 }
 
 }  // extern "C"

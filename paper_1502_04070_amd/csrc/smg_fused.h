@@ -1,0 +1,74 @@
+// Jobs of the fused kernels (see smg_fused.hip).
+#pragma once
+#include "smg_internal.h"
+
+namespace smg {
+
+// one fused normal-equation step: o = x (+ P z) + tau L^-1 A L^-1 (F - A (x (+ P z)))
+template <class T>
+struct NEJob {
+  LevelCoef<T> L;
+  const T* xu;
+  const T* xp;        // input iterate (not read when it is known to be zero)
+  const T* fu;
+  const T* fp;        // right-hand side
+  T* ou;
+  T* op;              // output iterate; must not alias the input
+  const T* zu;
+  const T* zp;        // coarse correction (coarse layout), added to x first
+  T tau;
+  double* partial;    // per tile: ||F - A x||^2 over the owned rows, or NULL
+  const int* done;
+};
+TileShape ne_tile_shape(int N);
+int ne_tiles(int N);
+template <class T>
+void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, hipStream_t s);
+
+// fused defect and restriction: (cu, cp) = P^T (F - A x), L = fine level
+template <class T>
+struct RRJob {
+  LevelCoef<T> L;
+  const T* xu;
+  const T* xp;
+  const T* fu;
+  const T* fp;
+  T* cu;
+  T* cp;
+  const int* done;
+};
+template <class T>
+void launch_resid_restrict(const RRJob<T>& J, hipStream_t s);
+
+// the iterate on levels 0..Lc by one workgroup
+constexpr int CC_MAX_LEVELS = 5;
+enum { CC_NE = 1, CC_UZAWA = 2, CC_RESTRICT = 3, CC_PROLONG = 4, CC_COARSE = 5 };
+inline int cc_op(int kind, int level, int zg) { return kind | (level << 8) | (zg << 16); }
+constexpr int CC_MAX_OPS = 256;
+
+template <class T>
+struct CoarseJob {
+  LevelCoef<T> L[CC_MAX_LEVELS + 1];
+  int n0, Lc, nc;
+  int nops;
+  const int* ops;        // device array of nops encoded operations
+  const double* cinv;    // bordered inverse of level 0 (column-major, nc x nc)
+  const T* fu;
+  const T* fp;           // right-hand side of level Lc (global)
+  T* xu;
+  T* xp;                 // iterate of level Lc (global; read unless zero_guess)
+  int zero_guess;
+  T tau, sigma;
+  const int* done;
+};
+size_t coarse_cycle_lds(int n0, int Lc, size_t elem);
+template <class T>
+int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s);
+template <class T>
+int coarse_cycle_allow_lds(size_t bytes);
+
+// p -= mean from partials (sum w p, sum w) pairs of np tiles
+void launch_project_partials(const double* mpart, int np, int N, double* p, const int* done,
+                             hipStream_t s);
+
+}  // namespace smg

@@ -1,0 +1,748 @@
+// Fused HIP kernels of the multigrid iterate (gfx950):
+//
+//   k_ne            one normal-equation smoothing step x <- x + tau L^-1 A L^-1 (F - A x)
+//                   (Section 4) in one launch: the intermediate L^-1 (F - A x)
+//                   lives only in LDS on the tile plus a halo of one square.
+//                   Optionally the coarse-grid correction x += P z (Section 3)
+//                   is applied to x while it is staged (the first
+//                   post-smoothing step absorbs the prolongation).
+//   k_resid_restrict  the defect F - A x and its restriction P^T (F - A x)
+//                   (Section 3) in one launch; the fine defect lives only in LDS.
+//   k_coarse_cycle  the whole iterate on the coarse levels (N <= 16) by one
+//                   workgroup with every vector of those levels in LDS,
+//                   including the exact solve on level 0.
+//   k_project_partials  the pressure mean projection from partial sums that
+//                   the residual-norm pass of the solve loop produces.
+//
+// Bandwidth: an unfused normal-equation step streams x, F and the
+// intermediate twice (6 vectors); k_ne streams x and F once and writes x once
+// (3 vectors).  k_resid_restrict reads x and F and writes a quarter-size
+// coarse vector instead of writing and re-reading the fine defect.
+#include "smg_cell.h"
+#include "smg_fused.h"
+
+namespace smg {
+
+// ---------------------------------------------------------------------------
+// prolongation weights (canonical embedding of coarse P2 functions)
+// ---------------------------------------------------------------------------
+
+template <int RA, int RB, class T, class FZ>
+__device__ __forceinline__ T pro_w(FZ Z) {
+  if constexpr (RA == 0 && RB == 0) return SMG_PRO_00(Z);
+  else if constexpr (RA == 0 && RB == 1) return SMG_PRO_01(Z);
+  else if constexpr (RA == 0 && RB == 2) return SMG_PRO_02(Z);
+  else if constexpr (RA == 0 && RB == 3) return SMG_PRO_03(Z);
+  else if constexpr (RA == 1 && RB == 0) return SMG_PRO_10(Z);
+  else if constexpr (RA == 1 && RB == 1) return SMG_PRO_11(Z);
+  else if constexpr (RA == 1 && RB == 2) return SMG_PRO_12(Z);
+  else if constexpr (RA == 1 && RB == 3) return SMG_PRO_13(Z);
+  else if constexpr (RA == 2 && RB == 0) return SMG_PRO_20(Z);
+  else if constexpr (RA == 2 && RB == 1) return SMG_PRO_21(Z);
+  else if constexpr (RA == 2 && RB == 2) return SMG_PRO_22(Z);
+  else if constexpr (RA == 2 && RB == 3) return SMG_PRO_23(Z);
+  else if constexpr (RA == 3 && RB == 0) return SMG_PRO_30(Z);
+  else if constexpr (RA == 3 && RB == 1) return SMG_PRO_31(Z);
+  else if constexpr (RA == 3 && RB == 2) return SMG_PRO_32(Z);
+  else return SMG_PRO_33(Z);
+}
+
+// Adds P z to the 16 fine lattice points (4I + ra, 4J + rb) of coarse square
+// (I, J): X(ra, rb) is a reference to the destination, IN(ra, rb) tells
+// whether the fine point is an interior velocity node, Z(dA, dB) reads the
+// coarse value at (2I + dA, 2J + dB) (zero outside the coarse interior).
+template <class T, class FX, class FIN, class FZ>
+__device__ __forceinline__ void pro_block(FX X, FIN IN, FZ Z) {
+#define SMG_PB(RA, RB) \
+  if (IN(RA, RB)) X(RA, RB) += pro_w<RA, RB, T>(Z);
+  SMG_PB(0, 0) SMG_PB(1, 0) SMG_PB(2, 0) SMG_PB(3, 0)
+  SMG_PB(0, 1) SMG_PB(1, 1) SMG_PB(2, 1) SMG_PB(3, 1)
+  SMG_PB(0, 2) SMG_PB(1, 2) SMG_PB(2, 2) SMG_PB(3, 2)
+  SMG_PB(0, 3) SMG_PB(1, 3) SMG_PB(2, 3) SMG_PB(3, 3)
+#undef SMG_PB
+}
+
+// P1 interpolation of coarse pressure zp (Nc+1 per side) at fine vertex (i, j)
+template <class T>
+__device__ __forceinline__ T pro_p1(const T* zp, int Nc, int i, int j) {
+  const int NPc = Nc + 1;
+  const int I = i >> 1, J = j >> 1;
+  auto Z = [&](int a, int b) -> T { return zp[(size_t)b * NPc + a]; };
+  if (!(i & 1) && !(j & 1)) return Z(I, J);
+  if ((i & 1) && !(j & 1)) return T(0.5) * (Z(I, J) + Z(I + 1, J));
+  if (!(i & 1) && (j & 1)) return T(0.5) * (Z(I, J) + Z(I, J + 1));
+  return T(0.5) * (Z(I, J) + Z(I + 1, J + 1));
+}
+
+// ---------------------------------------------------------------------------
+// k_ne: one fused normal-equation step on a TX x TY tile of squares
+// ---------------------------------------------------------------------------
+
+template <class T, int TX, int TY, bool ZG, bool PRO>
+__device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
+  constexpr int NT = 2 * TX * TY;
+  constexpr int XW = 2 * TX + 8, XH = 2 * TY + 8;      // x: lattice origin (2 i0 - 4, 2 j0 - 4)
+  constexpr int XPW = TX + 4, XPH = TY + 4;            // x pressure: origin (i0 - 2, j0 - 2)
+  constexpr int YW = 2 * TX + 4, YH = 2 * TY + 4;      // y: lattice origin (2 i0 - 2, 2 j0 - 2)
+  constexpr int YPW = TX + 2, YPH = TY + 2;            // y pressure: origin (i0 - 1, j0 - 1)
+  __shared__ T sx[2][XH][XW];
+  __shared__ T sxp[XPH * XPW];
+  __shared__ T sy[2][YH][YW];
+  __shared__ T syp[YPH * YPW];
+  __shared__ double red[NT / 64];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int ntx = (N + TX) / TX;
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+
+  // ---- stage 0: the iterate on the tile plus two squares of halo
+  if constexpr (!ZG) {
+    if constexpr (PRO) {
+      // one thread per coarse square of the window: 16 fine points each
+      constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;
+      const int Nc = N / 2, Mc = 2 * Nc + 1;
+      for (int e = tid; e < CW * CH; e += NT) {
+        const int ci = e % CW, cj = e / CW;
+        const int I = i0 / 2 - 1 + ci, Jc = j0 / 2 - 1 + cj;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          T z[3][3];
+#pragma unroll
+          for (int dB = 0; dB < 3; ++dB)
+#pragma unroll
+            for (int dA = 0; dA < 3; ++dA) {
+              const int A = 2 * I + dA, B = 2 * Jc + dB;
+              z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
+                              ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
+            }
+          auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
+          auto IN = [&](int ra, int rb) { return interior(4 * I + ra, 4 * Jc + rb); };
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int ra = 0; ra < 4; ++ra) {
+              const int a = 4 * I + ra, b = 4 * Jc + rb;
+              sx[c][4 * cj + rb][4 * ci + ra] =
+                  interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+            }
+          auto X = [&](int ra, int rb) -> T& { return sx[c][4 * cj + rb][4 * ci + ra]; };
+          pro_block<T>(X, IN, Z);
+        }
+      }
+      for (int e = tid; e < XPW * XPH; e += NT) {
+        const int li = e % XPW, lj = e / XPW;
+        const int i = i0 - 2 + li, j = j0 - 2 + lj;
+        T v = T(0);
+        if (i >= 0 && i <= N && j >= 0 && j <= N) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
+        sxp[e] = v;
+      }
+    } else {
+      for (int e = tid; e < XW * XH; e += NT) {
+        const int la = e % XW, lb = e / XW;
+        const int a = 2 * i0 - 4 + la, b = 2 * j0 - 4 + lb;
+        const bool in = interior(a, b);
+        const size_t g = (size_t)b * M + a;
+        sx[0][lb][la] = in ? J.xu[g] : T(0);
+        sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
+      }
+      for (int e = tid; e < XPW * XPH; e += NT) {
+        const int li = e % XPW, lj = e / XPW;
+        const int i = i0 - 2 + li, j = j0 - 2 + lj;
+        sxp[e] = (i >= 0 && i <= N && j >= 0 && j <= N) ? J.xp[(size_t)j * NP + i] : T(0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- stage 1: y = L^-1 (F - A x) on the tile plus one square of halo
+  double nrm = 0.0;
+  for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
+    const int ci = e % (TX + 2), cj = e / (TX + 2);
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    T y[9];
+    if constexpr (ZG) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) y[k] = T(0);
+    } else {
+      cell_apply<T, true, true, XH, XW, XPW>(J.L, sx, 2 * ci + 2, 2 * cj + 2, sxp, ci + 1, cj + 1, y);
+    }
+    const bool owned = ci >= 1 && ci <= TX && cj >= 1 && cj <= TY;
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i + DA, b = 2 * j + DB;
+      const bool in = interior(a, b);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T r = T(0);
+        if (in) r = J.fu[(size_t)c * M * M + (size_t)b * M + a] - y[2 * cls + c];
+        if (owned && in) nrm += (double)r * (double)r;
+        sy[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+      }
+    }
+    const bool inp = i >= 0 && i <= N && j >= 0 && j <= N;
+    T rp = T(0);
+    if (inp) rp = J.fp[(size_t)j * NP + i] - y[8];
+    if (owned && inp) nrm += (double)rp * (double)rp;
+    syp[cj * YPW + ci] = inp ? J.L.sinv[(size_t)j * NP + i] * rp : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 2: x_new = x + tau L^-1 A y on the tile; two threads per square
+  {
+    const int half = TX * TY;
+    const int part = tid / half, q = tid % half;
+    const int tx = q % TX, ty = q / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i <= N && j <= N) {
+      auto UA = [&](int c, int da, int db) -> T { return sy[c][2 * ty + 2 + db][2 * tx + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return syp[(ty + 1 + dj) * YPW + (tx + 1 + di)]; };
+      const T tau = J.tau;
+      auto emit = [&](int cls, T z0, T z1) {
+        const int DA = cls & 1, DB = cls >> 1;
+        const int a = 2 * i + DA, b = 2 * j + DB;
+        if (a > 2 * N || b > 2 * N) return;
+        const bool in = interior(a, b);
+        const size_t g = (size_t)b * M + a;
+        T x0 = T(0), x1 = T(0);
+        if constexpr (!ZG) {
+          x0 = sx[0][2 * ty + 4 + DB][2 * tx + 4 + DA];
+          x1 = sx[1][2 * ty + 4 + DB][2 * tx + 4 + DA];
+        }
+        const T d = J.L.adinv[cls] * tau;
+        J.ou[g] = in ? x0 + d * z0 : T(0);
+        J.ou[(size_t)M * M + g] = in ? x1 + d * z1 : T(0);
+      };
+      if (part == 0) {
+        T z0, z1;
+        {
+          auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, db); };
+          cell_vel<0, T, true, true>(J.L, Uc, PA, z0, z1);
+          emit(0, z0, z1);
+        }
+        {
+          auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, db); };
+          cell_vel<1, T, true, true>(J.L, Uc, PA, z0, z1);
+          emit(1, z0, z1);
+        }
+      } else {
+        T z0, z1;
+        {
+          auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, 1 + db); };
+          cell_vel<2, T, true, true>(J.L, Uc, PA, z0, z1);
+          emit(2, z0, z1);
+        }
+        {
+          auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, 1 + db); };
+          cell_vel<3, T, true, true>(J.L, Uc, PA, z0, z1);
+          emit(3, z0, z1);
+        }
+        auto U0 = [&](int da, int db) -> T { return UA(0, da, db); };
+        auto U1 = [&](int da, int db) -> T { return UA(1, da, db); };
+        const T zp = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+        const size_t g = (size_t)j * NP + i;
+        T xo = T(0);
+        if constexpr (!ZG) xo = sxp[(ty + 2) * XPW + tx + 2];
+        J.op[g] = xo + tau * J.L.sinv[g] * zp;
+      }
+    }
+  }
+  if (J.partial) {
+    const double s = wg_sum<NT>(nrm, red);
+    if (tid == 0) J.partial[tile] = s;
+  }
+}
+
+template <class T, int TX, int TY, bool ZG, bool PRO>
+__global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
+  if (J.done && *J.done) return;
+  ne_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+TileShape ne_tile_shape(int N) {
+  if (N >= 128) return {16, 8};
+  return {8, 8};
+}
+
+int ne_tiles(int N) {
+  const TileShape t = ne_tile_shape(N);
+  return ((N + t.tx) / t.tx) * ((N + t.ty) / t.ty);
+}
+
+template <class T, int TX, int TY>
+static void launch_ne_shape(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
+  const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
+  if (zg)
+    k_ne<T, TX, TY, true, false><<<nb, 2 * TX * TY, 0, s>>>(J);
+  else if (pro)
+    k_ne<T, TX, TY, false, true><<<nb, 2 * TX * TY, 0, s>>>(J);
+  else
+    k_ne<T, TX, TY, false, false><<<nb, 2 * TX * TY, 0, s>>>(J);
+}
+
+template <class T>
+void launch_ne(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
+  const TileShape t = ne_tile_shape(J.L.N);
+  if (t.tx == 16)
+    launch_ne_shape<T, 16, 8>(J, zg, pro, s);
+  else
+    launch_ne_shape<T, 8, 8>(J, zg, pro, s);
+}
+template void launch_ne<double>(const NEJob<double>&, bool, bool, hipStream_t);
+template void launch_ne<float>(const NEJob<float>&, bool, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// k_resid_restrict: F_c = P^T (F - A x) on an 8 x 8 tile of coarse squares
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
+  constexpr int TC = 8, NT = 256;
+  constexpr int XW = 4 * TC + 10;      // x: fine lattice origin (4 I0 - 6, 4 J0 - 6)
+  constexpr int XPW = 2 * TC + 5;      // x pressure: origin (2 I0 - 3, 2 J0 - 3)
+  constexpr int RW = 4 * TC + 6;       // defect: fine lattice origin (4 I0 - 4, 4 J0 - 4)
+  constexpr int RPW = 2 * TC + 3;      // defect pressure: origin (2 I0 - 2, 2 J0 - 2)
+  constexpr int NC1 = 2 * TC + 3;      // fine squares per side of stage 1
+  __shared__ T sx[2][XW][XW];
+  __shared__ T sxp[XPW * XPW];
+  __shared__ T sr[2][RW][RW];
+  __shared__ T srp[RPW * RPW];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int Nc = N / 2, Mc = 2 * Nc + 1, NPc = Nc + 1;
+  const int ntx = (Nc + TC) / TC;
+  const int I0 = (tile % ntx) * TC, J0 = (tile / ntx) * TC;
+  const int tid = threadIdx.x;
+  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+  for (int e = tid; e < XW * XW; e += NT) {
+    const int la = e % XW, lb = e / XW;
+    const int a = 4 * I0 - 6 + la, b = 4 * J0 - 6 + lb;
+    const bool in = interior(a, b);
+    const size_t g = (size_t)b * M + a;
+    sx[0][lb][la] = in ? J.xu[g] : T(0);
+    sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
+  }
+  for (int e = tid; e < XPW * XPW; e += NT) {
+    const int li = e % XPW, lj = e / XPW;
+    const int i = 2 * I0 - 3 + li, j = 2 * J0 - 3 + lj;
+    sxp[e] = (i >= 0 && i <= N && j >= 0 && j <= N) ? J.xp[(size_t)j * NP + i] : T(0);
+  }
+  __syncthreads();
+  // stage 1: fine defect on squares [2 I0 - 2, 2 I0 + 2 TC] per side
+  for (int e = tid; e < NC1 * NC1; e += NT) {
+    const int ci = e % NC1, cj = e / NC1;
+    const int i = 2 * I0 - 2 + ci, j = 2 * J0 - 2 + cj;
+    T y[9];
+    cell_apply<T, true, true, XW, XW, XPW>(J.L, sx, 2 * ci + 2, 2 * cj + 2, sxp, ci + 1, cj + 1, y);
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i + DA, b = 2 * j + DB;
+      const bool in = interior(a, b);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        sr[c][2 * cj + DB][2 * ci + DA] =
+            in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] - y[2 * cls + c] : T(0);
+    }
+    const bool inp = i >= 0 && i <= N && j >= 0 && j <= N;
+    srp[cj * RPW + ci] = inp ? J.fp[(size_t)j * NP + i] - y[8] : T(0);
+  }
+  __syncthreads();
+  // stage 2: one wave per coarse node class, one lane per coarse square
+  const int cls = tid >> 6, q = tid & 63;
+  const int tx = q % TC, ty = q / TC;
+  const int I = I0 + tx, Jc = J0 + ty;
+  if (I <= Nc && Jc <= Nc) {
+    const int CA = cls & 1, CB = cls >> 1;
+    const int A = 2 * I + CA, B = 2 * Jc + CB;
+    if (A <= 2 * Nc && B <= 2 * Nc) {
+      const bool in = A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc;
+      const int la = 4 * tx + 2 * CA + 4, lb = 4 * ty + 2 * CB + 4;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        auto R = [&](int fa, int fb) -> T { return sr[c][lb + fb][la + fa]; };
+        T v = T(0);
+        if (in) {
+          switch (cls) {
+            case 0: v = cell_res<0, T>(R); break;
+            case 1: v = cell_res<1, T>(R); break;
+            case 2: v = cell_res<2, T>(R); break;
+            default: v = cell_res<3, T>(R); break;
+          }
+        }
+        J.cu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] = v;
+      }
+    }
+    if (cls == 3) {
+      auto Rp = [&](int di, int dj) -> T { return srp[(2 * ty + 2 + dj) * RPW + (2 * tx + 2 + di)]; };
+      J.cp[(size_t)Jc * NPc + I] =
+          Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1));
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_resid_restrict(RRJob<T> J) {
+  if (J.done && *J.done) return;
+  rr_tile<T>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class T>
+void launch_resid_restrict(const RRJob<T>& J, hipStream_t s) {
+  const int Nc = J.L.N / 2;
+  const int nb = ((Nc + 8) / 8) * ((Nc + 8) / 8);
+  k_resid_restrict<T><<<nb, 256, 0, s>>>(J);
+}
+template void launch_resid_restrict<double>(const RRJob<double>&, hipStream_t);
+template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// k_coarse_cycle: the iterate on levels 0..Lc in one workgroup, all in LDS
+// ---------------------------------------------------------------------------
+// Per level l the LDS holds three vectors X, F, T; a vector is a velocity
+// lattice padded by two points on every side, (2N+5)^2 per component, then a
+// pressure lattice padded by one vertex, (N+3)^2, all zero outside the interior.
+
+struct CLay {
+  int N, Mp, NPp, vlen;  // padded sizes
+  int off;               // offset of X of this level in the LDS array (F, T follow)
+};
+
+__device__ __forceinline__ CLay clay(int n0, int l, int base_off) {
+  CLay c;
+  c.N = n0 << l;
+  c.Mp = 2 * c.N + 5;
+  c.NPp = c.N + 3;
+  c.vlen = 2 * c.Mp * c.Mp + c.NPp * c.NPp;
+  c.off = base_off;
+  return c;
+}
+
+template <class T>
+struct CVec {
+  T* v;
+  int N, Mp, NPp;
+  __device__ __forceinline__ T& u(int c, int a, int b) const { return v[(c * Mp + b + 2) * Mp + a + 2]; }
+  __device__ __forceinline__ T& p(int i, int j) const { return v[2 * Mp * Mp + (j + 1) * NPp + i + 1]; }
+};
+
+template <class T>
+__device__ __forceinline__ void cc_cell(const LevelCoef<T>& L, const CVec<T>& X, int i, int j, T y[9]) {
+  auto UA = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + db); };
+  auto PA = [&](int di, int dj) -> T { return X.p(i + di, j + dj); };
+  cell_apply_acc<T, true, true>(L, UA, PA, y);
+}
+
+template <class T>
+__global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
+  if (J.done && *J.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int Lc = J.Lc, n0 = J.n0;
+  int offs[CC_MAX_LEVELS + 2];
+  {
+    int o = 0;
+    for (int l = 0; l <= Lc; ++l) {
+      offs[l] = o;
+      o += 3 * clay(n0, l, 0).vlen;
+    }
+    offs[Lc + 1] = o;
+  }
+  auto vec = [&](int l, int k) -> CVec<T> {
+    const CLay c = clay(n0, l, offs[l]);
+    return CVec<T>{sm + c.off + k * c.vlen, c.N, c.Mp, c.NPp};
+  };
+  // zero everything (padding must be zero), then load F (and X) of level Lc
+  for (int e = tid; e < offs[Lc + 1]; e += nt) sm[e] = T(0);
+  __syncthreads();
+  {
+    const CVec<T> X = vec(Lc, 0), F = vec(Lc, 1);
+    const int N = X.N, M = 2 * N + 1, NP = N + 1;
+    for (int e = tid; e < 2 * M * M; e += nt) {
+      const int c = e / (M * M), q = e % (M * M), a = q % M, b = q / M;
+      if (a > 0 && a < 2 * N && b > 0 && b < 2 * N) {
+        F.u(c, a, b) = J.fu[e];
+        if (!J.zero_guess) X.u(c, a, b) = J.xu[e];
+      }
+    }
+    for (int e = tid; e < NP * NP; e += nt) {
+      F.p(e % NP, e / NP) = J.fp[e];
+      if (!J.zero_guess) X.p(e % NP, e / NP) = J.xp[e];
+    }
+  }
+  __syncthreads();
+  const T tau = J.tau, sigma = J.sigma;
+  for (int k = 0; k < J.nops; ++k) {
+    const int op = J.ops[k];
+    const int kind = op & 0xff, l = (op >> 8) & 0xff;
+    // the entry level starts from zero only if the caller says so
+    const int zg = ((op >> 16) & 1) && (l < Lc || J.zero_guess);
+    const LevelCoef<T>& L = J.L[l];
+    const CVec<T> X = vec(l, 0), F = vec(l, 1), Tv = vec(l, 2);
+    const int N = X.N, NP = N + 1, ncell = NP * NP;
+    auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+    if (kind == CC_NE) {
+      // t = L^-1 (F - A x); x = x + tau L^-1 A t
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        T y[9];
+        if (zg) {
+          for (int q = 0; q < 9; ++q) y[q] = T(0);
+        } else {
+          cc_cell<T>(L, X, i, j, y);
+        }
+        for (int cls = 0; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (!interior(a, b)) continue;
+          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = L.adinv[cls] * (F.u(c, a, b) - y[2 * cls + c]);
+        }
+        Tv.p(i, j) = L.sinv[e] * (F.p(i, j) - y[8]);
+      }
+      __syncthreads();
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        T y[9];
+        cc_cell<T>(L, Tv, i, j, y);
+        for (int cls = 0; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (!interior(a, b)) continue;
+          for (int c = 0; c < 2; ++c) {
+            const T x0 = zg ? T(0) : X.u(c, a, b);
+            X.u(c, a, b) = x0 + tau * L.adinv[cls] * y[2 * cls + c];
+          }
+        }
+        const T p0 = zg ? T(0) : X.p(i, j);
+        X.p(i, j) = p0 + tau * L.sinv[e] * y[8];
+      }
+      __syncthreads();
+    } else if (kind == CC_UZAWA) {
+      // t.u = u + tau Ahat^-1 (f - A u - B^T p)
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        T y[9];
+        if (zg) {
+          for (int q = 0; q < 9; ++q) y[q] = T(0);
+        } else {
+          cc_cell<T>(L, X, i, j, y);
+        }
+        for (int cls = 0; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (!interior(a, b)) continue;
+          for (int c = 0; c < 2; ++c) {
+            const T x0 = zg ? T(0) : X.u(c, a, b);
+            Tv.u(c, a, b) = x0 + tau * L.adinv[cls] * (F.u(c, a, b) - y[2 * cls + c]);
+          }
+        }
+      }
+      __syncthreads();
+      // t.p = dp = -sigma Shat^-1 (g - B t.u)
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        auto U0 = [&](int da, int db) -> T { return Tv.u(0, 2 * i + da, 2 * j + db); };
+        auto U1 = [&](int da, int db) -> T { return Tv.u(1, 2 * i + da, 2 * j + db); };
+        const T bu = L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+        Tv.p(i, j) = -sigma * L.sinv[e] * (F.p(i, j) - bu);
+      }
+      __syncthreads();
+      // x.u = t.u - tau Ahat^-1 B^T dp ; x.p = p + dp
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        auto PA = [&](int di, int dj) -> T { return Tv.p(i + di, j + dj); };
+        for (int cls = 1; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (!interior(a, b)) continue;
+          T bx, by;
+          if (cls == 1) { bx = cell_btx<1, T>(PA); by = cell_bty<1, T>(PA); }
+          else if (cls == 2) { bx = cell_btx<2, T>(PA); by = cell_bty<2, T>(PA); }
+          else { bx = cell_btx<3, T>(PA); by = cell_bty<3, T>(PA); }
+          X.u(0, a, b) = Tv.u(0, a, b) - tau * L.adinv[cls] * L.h * bx;
+          X.u(1, a, b) = Tv.u(1, a, b) - tau * L.adinv[cls] * L.h * by;
+        }
+        {
+          const int a = 2 * i, b = 2 * j;   // vertex nodes: no pressure coupling
+          if (interior(a, b)) {
+            X.u(0, a, b) = Tv.u(0, a, b);
+            X.u(1, a, b) = Tv.u(1, a, b);
+          }
+        }
+        const T p0 = zg ? T(0) : X.p(i, j);
+        X.p(i, j) = p0 + Tv.p(i, j);
+      }
+      __syncthreads();
+    } else if (kind == CC_RESTRICT) {
+      // T = F - A X on level l, then F_{l-1} = P^T T (and X_{l-1} = 0)
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP;
+        T y[9];
+        cc_cell<T>(L, X, i, j, y);
+        for (int cls = 0; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (!interior(a, b)) continue;
+          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = F.u(c, a, b) - y[2 * cls + c];
+        }
+        Tv.p(i, j) = F.p(i, j) - y[8];
+      }
+      __syncthreads();
+      const CVec<T> Fc = vec(l - 1, 1), Xc = vec(l - 1, 0);
+      const int Nc = Fc.N, NPc = Nc + 1;
+      for (int e = tid; e < NPc * NPc; e += nt) {
+        const int I = e % NPc, Jc = e / NPc;
+        for (int cls = 0; cls < 4; ++cls) {
+          const int A = 2 * I + (cls & 1), B = 2 * Jc + (cls >> 1);
+          if (!(A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)) continue;
+          for (int c = 0; c < 2; ++c) {
+            auto R = [&](int fa, int fb) -> T { return Tv.u(c, 2 * A + fa, 2 * B + fb); };
+            T v;
+            if (cls == 0) v = cell_res<0, T>(R);
+            else if (cls == 1) v = cell_res<1, T>(R);
+            else if (cls == 2) v = cell_res<2, T>(R);
+            else v = cell_res<3, T>(R);
+            Fc.u(c, A, B) = v;
+            Xc.u(c, A, B) = T(0);
+          }
+        }
+        auto Rp = [&](int di, int dj) -> T {
+          const int fi = 2 * I + di, fj = 2 * Jc + dj;
+          return (fi >= 0 && fi <= N && fj >= 0 && fj <= N) ? Tv.p(fi, fj) : T(0);
+        };
+        Fc.p(I, Jc) = Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1));
+        Xc.p(I, Jc) = T(0);
+      }
+      __syncthreads();
+    } else if (kind == CC_PROLONG) {
+      // X_l += P X_{l-1}: one thread per coarse square, 16 fine points each
+      const CVec<T> Xc = vec(l - 1, 0);
+      const int Nc = Xc.N, NPc = Nc + 1;
+      for (int e = tid; e < NPc * NPc; e += nt) {
+        const int I = e % NPc, Jc = e / NPc;
+        for (int c = 0; c < 2; ++c) {
+          auto Z = [&](int dA, int dB) -> T { return Xc.u(c, 2 * I + dA, 2 * Jc + dB); };
+          auto IN = [&](int ra, int rb) { return interior(4 * I + ra, 4 * Jc + rb); };
+          auto XR = [&](int ra, int rb) -> T& { return X.u(c, 4 * I + ra, 4 * Jc + rb); };
+          pro_block<T>(XR, IN, Z);
+        }
+      }
+      for (int e = tid; e < ncell; e += nt) {
+        const int i = e % NP, j = e / NP, I = i >> 1, Jc = j >> 1;
+        T z;
+        if (!(i & 1) && !(j & 1)) z = Xc.p(I, Jc);
+        else if ((i & 1) && !(j & 1)) z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I + 1, Jc));
+        else if (!(i & 1) && (j & 1)) z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I, Jc + 1));
+        else z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I + 1, Jc + 1));
+        X.p(i, j) += z;
+      }
+      __syncthreads();
+    } else if (kind == CC_COARSE) {
+      // exact solve on level 0: z = Cinv [F; 0] in the compact order
+      const int M0 = 2 * N + 1, ni = 2 * N - 1, nu = ni * ni;
+      const int nc = J.nc;
+      T* r = Tv.v;  // reuse T of level 0 as the compact right-hand side
+      for (int k2 = tid; k2 < nc; k2 += nt) {
+        T v = T(0);
+        if (k2 < 2 * nu) {
+          const int c = k2 / nu, q = k2 % nu;
+          v = F.u(c, 1 + q % ni, 1 + q / ni);
+        } else if (k2 < 2 * nu + NP * NP) {
+          const int q = k2 - 2 * nu;
+          v = F.p(q % NP, q / NP);
+        }
+        r[k2] = v;
+      }
+      __syncthreads();
+      T zr[4];
+      int cnt = 0;
+      for (int row = tid; row < nc && cnt < 4; row += nt, ++cnt) {
+        double z = 0.0;
+        for (int q = 0; q < nc; ++q) z += J.cinv[(size_t)q * nc + row] * (double)r[q];
+        zr[cnt] = (T)z;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int row = tid; row < nc && cnt < 4; row += nt, ++cnt) {
+        if (row < 2 * nu) {
+          const int c = row / nu, q = row % nu;
+          X.u(c, 1 + q % ni, 1 + q / ni) = zr[cnt];
+        } else if (row < 2 * nu + NP * NP) {
+          const int q = row - 2 * nu;
+          X.p(q % NP, q / NP) = zr[cnt];
+        }
+      }
+      __syncthreads();
+      (void)M0;
+    }
+  }
+  // store X of level Lc
+  {
+    const CVec<T> X = vec(Lc, 0);
+    const int N = X.N, M = 2 * N + 1, NP = N + 1;
+    for (int e = tid; e < 2 * M * M; e += nt) {
+      const int c = e / (M * M), q = e % (M * M), a = q % M, b = q / M;
+      J.xu[e] = (a > 0 && a < 2 * N && b > 0 && b < 2 * N) ? X.u(c, a, b) : T(0);
+    }
+    for (int e = tid; e < NP * NP; e += nt) J.xp[e] = X.p(e % NP, e / NP);
+  }
+}
+
+size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
+  size_t tot = 0;
+  for (int l = 0; l <= Lc; ++l) {
+    const size_t N = (size_t)n0 << l, Mp = 2 * N + 5, NPp = N + 3;
+    tot += 3 * (2 * Mp * Mp + NPp * NPp);
+  }
+  return tot * elem;
+}
+
+template <class T>
+int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s) {
+  const size_t lds = coarse_cycle_lds(J.n0, J.Lc, sizeof(T));
+  k_coarse_cycle<T><<<1, 512, lds, s>>>(J);
+  return 0;
+}
+template int launch_coarse_cycle<double>(const CoarseJob<double>&, hipStream_t);
+template int launch_coarse_cycle<float>(const CoarseJob<float>&, hipStream_t);
+
+template <class T>
+int coarse_cycle_allow_lds(size_t bytes) {
+  return (int)hipFuncSetAttribute((const void*)k_coarse_cycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+template int coarse_cycle_allow_lds<double>(size_t);
+template int coarse_cycle_allow_lds<float>(size_t);
+
+// ---------------------------------------------------------------------------
+// pressure mean projection from tile partials (sum_i w_i p_i, sum_i w_i)
+// written by the residual-norm pass; every block reduces them in the same
+// order and subtracts the mean from its part of p.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_project_partials(const double* __restrict__ mpart, int np, int N,
+                                                          double* p, const int* done) {
+  if (done && *done) return;
+  __shared__ double red[4];
+  __shared__ double sh_mean;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) {
+    s1 += mpart[2 * k];
+    s2 += mpart[2 * k + 1];
+  }
+  const double t1 = wg_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = wg_sum<256>(s2, red);
+  if (threadIdx.x == 0) sh_mean = t1 / t2;
+  __syncthreads();
+  const int n = (N + 1) * (N + 1);
+  const double m = sh_mean;
+  for (int k = 0; k < 4; ++k) {
+    const int e = blockIdx.x * 1024 + k * 256 + threadIdx.x;
+    if (e < n) p[e] -= m;
+  }
+}
+
+void launch_project_partials(const double* mpart, int np, int N, double* p, const int* done,
+                             hipStream_t s) {
+  const int n = (N + 1) * (N + 1);
+  k_project_partials<<<(n + 1023) / 1024, 256, 0, s>>>(mpart, np, N, p, done);
+}
+
+}  // namespace smg

@@ -39,6 +39,7 @@ struct StencilJob {
   T w_u, w_p;          // weights of the velocity / pressure rows
   int diag_u, diag_p;  // 1: scale by Ahat^-1 / Shat^-1, 0: no scaling
   double* partial;     // per-tile partial sums, or NULL
+  double* mean_partial;  // per tile: (sum w_i p_i, sum w_i) of in_p, or NULL
   const int* done;     // if non-NULL and *done != 0 the launch does nothing
 };
 

@@ -87,19 +87,44 @@ __device__ __forceinline__ T res_row(FR R) {
 // generic fused stencil: out = base + w D (rhs - calA in)
 // ---------------------------------------------------------------------------
 
-template <int CLS, class T, int WX, int WY, int PX, int PY, int ROWS>
+// Operation flags of the fused stencil.  F = 0 selects the generic kernel,
+// which tests every pointer at run time; any other value is a compile-time
+// specialization in which absent operands are known to be absent.
+enum : unsigned {
+  F_ROWS_U = 1u, F_ROWS_P = 2u, F_IN_U = 4u, F_IN_P = 8u, F_RHS_U = 16u, F_RHS_P = 32u,
+  F_BASE_U = 64u, F_BASE_P = 128u, F_DIAG_U = 256u, F_DIAG_P = 512u, F_OUT_U = 1024u,
+  F_OUT_P = 2048u, F_PARTIAL = 4096u, F_PSUB = 8192u, F_MEAN = 16384u
+};
+
+template <unsigned F>
+struct Flags {
+  template <class P>
+  static __device__ __forceinline__ bool on(unsigned flag, P ptr) {
+    if constexpr (F == 0) return ptr != nullptr;
+    else return (F & flag) != 0;
+  }
+  static __device__ __forceinline__ bool on_int(unsigned flag, int v) {
+    if constexpr (F == 0) return v != 0;
+    else return (F & flag) != 0;
+  }
+};
+
+template <int CLS, unsigned F, class T, int WX, int WY, int PX, int PY>
 __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY][WX],
                                               T (*sp)[PX], int tx, int ty, int i, int j,
-                                              bool hu, bool hp, double& nrm) {
+                                              double& nrm) {
+  using FL = Flags<F>;
   constexpr int DA = CLS & 1, DB = CLS >> 1;
   const int N = J.L.N, M = 2 * N + 1;
   const int a = 2 * i + DA, b = 2 * j + DB;
   if (a > 2 * N || b > 2 * N) return;
   const bool interior = (a > 0) && (a < 2 * N) && (b > 0) && (b < 2 * N);
   const int la = 2 * tx + 2 + DA, lb = 2 * ty + 2 + DB;
+  const bool hu = FL::on(F_IN_U, J.in_u);
+  const bool hp = FL::on(F_IN_P, J.in_p);
   auto C = [&](int g) -> T { return J.L.acoef[CLS][g]; };
   auto P = [&](int di, int dj) -> T { return sp[ty + 1 + dj][tx + 1 + di]; };
-  const T dscale = J.diag_u ? J.L.adinv[CLS] : T(1);
+  const T dscale = FL::on_int(F_DIAG_U, J.diag_u) ? J.L.adinv[CLS] : T(1);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     auto U = [&](int da, int db) -> T { return su[c][lb + db][la + da]; };
@@ -107,17 +132,18 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
     if (hu) y += a_row<CLS, T>(U, C);
     if (hp) y += J.L.h * (c == 0 ? btx_row<CLS, T>(P) : bty_row<CLS, T>(P));
     const size_t g = (size_t)c * M * M + (size_t)b * M + a;
-    const T r = (J.rhs_u ? J.rhs_u[g] : T(0)) - y;
-    if (interior) nrm += (double)r * (double)r;
-    if (J.out_u) {
-      const T v = (J.base_u ? J.base_u[g] : T(0)) + J.w_u * dscale * r;
+    const T r = (FL::on(F_RHS_U, J.rhs_u) ? J.rhs_u[g] : T(0)) - y;
+    if (FL::on(F_PARTIAL, J.partial) && interior) nrm += (double)r * (double)r;
+    if (FL::on(F_OUT_U, J.out_u)) {
+      const T v = (FL::on(F_BASE_U, J.base_u) ? J.base_u[g] : T(0)) + J.w_u * dscale * r;
       J.out_u[g] = interior ? v : T(0);
     }
   }
 }
 
-template <class T, int TX, int TY, int ROWS>
+template <class T, int TX, int TY, unsigned F>
 __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
+  using FL = Flags<F>;
   constexpr int NT = TX * TY;
   constexpr int WX = 2 * TX + 4, WY = 2 * TY + 4;
   constexpr int PX = TX + 2, PY = TY + 2;
@@ -128,8 +154,10 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   const int ntx = (N + TX) / TX;
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
-  const bool hu = J.in_u != nullptr;
-  const bool hp = (ROWS & ROWS_U) && J.in_p != nullptr;
+  const bool rows_u = (F == 0) ? (J.out_u != nullptr || J.partial != nullptr) : (F & F_ROWS_U) != 0;
+  const bool rows_p = (F == 0) ? (J.out_p != nullptr || J.partial != nullptr) : (F & F_ROWS_P) != 0;
+  const bool hu = FL::on(F_IN_U, J.in_u);
+  const bool hp = rows_u && FL::on(F_IN_P, J.in_p);
   if (hu) {
     for (int e = tid; e < WX * WY; e += NT) {
       const int la = e % WX, lb = e / WX;
@@ -147,51 +175,68 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       T v = T(0);
       if (i >= 0 && i <= N && j >= 0 && j <= N) {
         v = J.in_p[(size_t)j * NP + i];
-        if (J.in_p_sub) v -= J.in_p_sub[(size_t)j * NP + i];
+        if (FL::on(F_PSUB, J.in_p_sub)) v -= J.in_p_sub[(size_t)j * NP + i];
       }
       sp[lj][li] = v;
     }
   }
-  __syncthreads();
+  if (hu || hp) __syncthreads();
   const int tx = tid % TX, ty = tid / TX;
   const int i = i0 + tx, j = j0 + ty;
   double nrm = 0.0;
   if (i <= N && j <= N) {
-    if constexpr ((ROWS & ROWS_U) != 0) {
-      velocity_node<0, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
-      velocity_node<1, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
-      velocity_node<2, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
-      velocity_node<3, T, WX, WY, PX, PY, ROWS>(J, su, sp, tx, ty, i, j, hu, hp, nrm);
+    if (rows_u) {
+      velocity_node<0, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<1, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<2, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<3, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
     }
-    if constexpr ((ROWS & ROWS_P) != 0) {
+    if (rows_p) {
       const int la = 2 * tx + 2, lb = 2 * ty + 2;
       auto U0 = [&](int da, int db) -> T { return su[0][lb + db][la + da]; };
       auto U1 = [&](int da, int db) -> T { return su[1][lb + db][la + da]; };
       const T y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
       const size_t g = (size_t)j * NP + i;
-      const T r = (J.rhs_p ? J.rhs_p[g] : T(0)) - y;
-      nrm += (double)r * (double)r;
-      if (J.out_p) {
-        const T d = J.diag_p ? J.L.sinv[g] : T(1);
-        J.out_p[g] = (J.base_p ? J.base_p[g] : T(0)) + J.w_p * d * r;
+      const T r = (FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y;
+      if (FL::on(F_PARTIAL, J.partial)) nrm += (double)r * (double)r;
+      if (FL::on(F_OUT_P, J.out_p)) {
+        const T d = FL::on_int(F_DIAG_P, J.diag_p) ? J.L.sinv[g] : T(1);
+        J.out_p[g] = (FL::on(F_BASE_P, J.base_p) ? J.base_p[g] : T(0)) + J.w_p * d * r;
       }
     }
   }
-  if (J.partial) {
+  if (FL::on(F_PARTIAL, J.partial)) {
     const double s = block_sum<NT>(nrm, red);
     if (tid == 0) J.partial[tile] = s;
   }
+  if (FL::on(F_MEAN, J.mean_partial)) {
+    // pressure mean pieces of in_p over the owned vertices
+    double w = 0.0, wp = 0.0;
+    if (i <= N && j <= N) {
+      const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
+      w = (!bi && !bj) ? 1.0 : (bi != bj) ? 0.5 : (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
+      wp = w * (double)sp[ty + 1][tx + 1];
+    }
+    __syncthreads();
+    const double s1 = block_sum<NT>(wp, red);
+    __syncthreads();
+    const double s2 = block_sum<NT>(w, red);
+    if (tid == 0) {
+      J.mean_partial[2 * tile] = s1;
+      J.mean_partial[2 * tile + 1] = s2;
+    }
+  }
 }
 
-template <class T, int TX, int TY, int ROWS>
+template <class T, int TX, int TY, unsigned F>
 __global__ __launch_bounds__(TX* TY) void k_stencil(StencilJob<T> J) {
   if (J.done && *J.done) return;
-  stencil_tile<T, TX, TY, ROWS>(J, xcd_swizzle(blockIdx.x, gridDim.x));
+  stencil_tile<T, TX, TY, F>(J, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 TileShape stencil_tile(int N) {
   if (N >= 512) return {16, 16};
-  if (N >= 256) return {16, 8};
+  if (N >= 128) return {16, 8};
   return {8, 8};
 }
 
@@ -200,15 +245,68 @@ int stencil_tiles(int N) {
   return ((N + t.tx) / t.tx) * ((N + t.ty) / t.ty);
 }
 
+// operation modes used by the library (anything else runs the generic kernel)
+constexpr unsigned RW_UP = F_ROWS_U | F_ROWS_P;
+constexpr unsigned OUT_UP = F_OUT_U | F_OUT_P;
+constexpr unsigned M_APPLY = RW_UP | F_IN_U | F_IN_P | OUT_UP;
+constexpr unsigned M_RESID = RW_UP | F_IN_U | F_IN_P | F_RHS_U | F_RHS_P | OUT_UP;
+constexpr unsigned M_RESID_NORM = RW_UP | F_IN_U | F_IN_P | F_RHS_U | F_RHS_P | F_PARTIAL;
+constexpr unsigned M_RESID_NORM_MEAN = M_RESID_NORM | F_MEAN;
+constexpr unsigned M_RESID_BOTH_MEAN = M_RESID_NORM_MEAN | OUT_UP;
+constexpr unsigned M_RESID_BOTH = M_RESID | F_PARTIAL;
+constexpr unsigned M_NE1 = M_RESID | F_DIAG_U | F_DIAG_P;
+constexpr unsigned M_NE1Z = RW_UP | F_RHS_U | F_RHS_P | F_DIAG_U | F_DIAG_P | OUT_UP;
+constexpr unsigned M_NE2 = M_APPLY | F_BASE_U | F_BASE_P | F_DIAG_U | F_DIAG_P;
+constexpr unsigned M_NE2Z = M_APPLY | F_DIAG_U | F_DIAG_P;
+constexpr unsigned M_UZ1 = F_ROWS_U | F_IN_U | F_IN_P | F_RHS_U | F_BASE_U | F_DIAG_U | F_OUT_U;
+constexpr unsigned M_UZ1Z = F_ROWS_U | F_RHS_U | F_DIAG_U | F_OUT_U;
+constexpr unsigned M_UZ2 = F_ROWS_P | F_IN_U | F_RHS_P | F_DIAG_P | F_OUT_P;
+constexpr unsigned M_UZ3 = RW_UP | F_IN_P | F_RHS_P | F_BASE_U | F_BASE_P | F_DIAG_U | OUT_UP;
+constexpr unsigned M_UZ3Z = RW_UP | F_IN_P | F_RHS_P | F_BASE_U | F_DIAG_U | OUT_UP;
+constexpr unsigned M_MASK_U = F_ROWS_U | F_RHS_U | F_OUT_U;
+
+template <class T>
+unsigned job_flags(const StencilJob<T>& J, int rows) {
+  unsigned f = 0;
+  if (rows & ROWS_U) f |= F_ROWS_U;
+  if (rows & ROWS_P) f |= F_ROWS_P;
+  if (J.in_u) f |= F_IN_U;
+  if (J.in_p && (rows & ROWS_U)) f |= F_IN_P;
+  if (J.in_p_sub && (rows & ROWS_U)) f |= F_PSUB;
+  if (J.rhs_u && (rows & ROWS_U)) f |= F_RHS_U;
+  if (J.rhs_p && (rows & ROWS_P)) f |= F_RHS_P;
+  if (J.base_u && (rows & ROWS_U)) f |= F_BASE_U;
+  if (J.base_p && (rows & ROWS_P)) f |= F_BASE_P;
+  if (J.diag_u && (rows & ROWS_U)) f |= F_DIAG_U;
+  if (J.diag_p && (rows & ROWS_P)) f |= F_DIAG_P;
+  if (J.out_u && (rows & ROWS_U)) f |= F_OUT_U;
+  if (J.out_p && (rows & ROWS_P)) f |= F_OUT_P;
+  if (J.partial) f |= F_PARTIAL;
+  if (J.mean_partial && J.in_p && (rows & ROWS_U)) f |= F_MEAN;
+  return f;
+}
+
 template <class T, int TX, int TY>
 static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s) {
   const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
-  if (rows == ROWS_U)
-    k_stencil<T, TX, TY, ROWS_U><<<nb, TX * TY, 0, s>>>(J);
-  else if (rows == ROWS_P)
-    k_stencil<T, TX, TY, ROWS_P><<<nb, TX * TY, 0, s>>>(J);
-  else
-    k_stencil<T, TX, TY, ROWS_UP><<<nb, TX * TY, 0, s>>>(J);
+  const unsigned f = job_flags(J, rows);
+#define SMG_CASE(MODE) \
+  case MODE: k_stencil<T, TX, TY, MODE><<<nb, TX * TY, 0, s>>>(J); return;
+  switch (f) {
+    SMG_CASE(M_APPLY) SMG_CASE(M_RESID) SMG_CASE(M_RESID_NORM) SMG_CASE(M_RESID_BOTH)
+    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
+    SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
+    SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
+    SMG_CASE(M_MASK_U)
+    default: break;
+  }
+#undef SMG_CASE
+  // generic kernel: rows are selected by the output / partial pointers, so
+  // clear the pointers of the rows that were not asked for
+  StencilJob<T> G = J;
+  if (!(rows & ROWS_U)) { G.out_u = nullptr; }
+  if (!(rows & ROWS_P)) { G.out_p = nullptr; }
+  k_stencil<T, TX, TY, 0u><<<nb, TX * TY, 0, s>>>(G);
 }
 
 template <class T>

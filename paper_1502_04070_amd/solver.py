@@ -40,7 +40,7 @@ class Hierarchy:
 
     def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
                  sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
-                 n0: int = 2, device=None):
+                 n0: int = 2, fused: bool = True, device=None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -51,7 +51,7 @@ class Hierarchy:
         if tau is None:
             tau = 0.35 if smoother == "ne" else 0.8
         self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma),
-                                     int(nu_pre), int(nu_post), int(gamma), int(n0))
+                                     int(nu_pre), int(nu_post), int(gamma), int(n0), 0 if fused else 1)
         self.N, self.beta, self.smoother = int(N), float(beta), smoother
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -185,6 +185,13 @@ class Hierarchy:
         _lib.check(self.lib.smg_dot(self.h, level, int(which), _ptr(a), _ptr(b), _ptr(out), _stream()),
                    "smg_dot")
         return out
+
+    def time_kernel(self, which: int, reps: int = 50) -> float:
+        """Mean duration (ms) of one finest-level stencil kernel (see smg_time_kernel)."""
+        ms = C.c_double()
+        _lib.check(self.lib.smg_time_kernel(self.h, int(which), int(reps), C.byref(ms), _stream()),
+                   "smg_time_kernel")
+        return ms.value
 
     # -- iterates ----------------------------------------------------------------
     def cycle(self, fu, gp, u, p):

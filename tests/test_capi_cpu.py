@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_default_params(lib):
     p = _lib.SmgParams()
     assert lib.smg_default_params(C.byref(p)) == 0
-    assert (p.smoother, p.tau, p.sigma, p.nu_pre, p.nu_post, p.gamma, p.n0) == (0, 0.35, 0.8, 2, 2, 1, 2)
+    assert (p.smoother, p.tau, p.sigma, p.nu_pre, p.nu_post, p.gamma, p.n0, p.unfused) == (0, 0.35, 0.8, 2, 2, 1, 2, 0)
 
 
 @pytest.mark.parametrize("N,beta,mod,needle", [

@@ -40,13 +40,14 @@ def _params(kind):
             "ne_0pre": (dict(smoother="ne", nu_pre=0, nu_post=2), mg.Params("ne", 0.35, 0.8, 0, 2, 1))}[kind]
 
 
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
 @pytest.mark.parametrize("kind", ["ne", "uzawa", "ne_w", "uzawa_w", "ne_11", "ne_0pre"])
-@pytest.mark.parametrize("N,n0,beta", [(8, 4, 1.0), (32, 2, 0.0), (32, 2, 1e4), (48, 3, 1e6)])
-def test_iterates_match_oracle(kind, N, n0, beta):
-    print(f"cycle {kind} N={N} n0={n0} beta={beta}", flush=True)
+@pytest.mark.parametrize("N,n0,beta", [(8, 4, 1.0), (32, 2, 0.0), (32, 2, 1e4), (48, 3, 1e6), (64, 2, 3.0)])
+def test_iterates_match_oracle(kind, N, n0, beta, fused):
+    print(f"cycle {kind} N={N} n0={n0} beta={beta} fused={fused}", flush=True)
     gkw, prm = _params(kind)
     oh = oracle_level(N, beta, n0)
-    gh = gpu_hier(N, beta, n0=n0, **gkw)
+    gh = gpu_hier(N, beta, n0=n0, fused=fused, **gkw)
     F, G = inputs.normal_fg(N, seed=21)
     f, FU, GP = _rhs(gh, oh, F, G)
     d = oh.discs[-1]
@@ -62,12 +63,20 @@ def test_iterates_match_oracle(kind, N, n0, beta):
 
 @pytest.mark.parametrize("beta", [0.0, 1.0, 1e2, 1e4, 1e6])
 def test_solve_full_size_matches_oracle(beta):
+    _solve_full_size(beta)
+
+
+def test_solve_full_size_unfused_matches_oracle():
+    _solve_full_size(1.0, fused=False)
+
+
+def _solve_full_size(beta, fused=True):
     """N = 128 (66049 P2 nodes per component, 16641 P1 nodes), f iid U[-1,1]
     (seed 0), g = 0, NE V(2,2) to 1e-8: same iterate count, same solution."""
     N = 128
     print(f"solve N={N} beta={beta}", flush=True)
     oh = oracle_level(N, beta, 2)
-    gh = gpu_hier(N, beta)
+    gh = gpu_hier(N, beta, fused=fused)
     F, G = inputs.uniform_f(N, seed=0)
     f, FU, GP = _rhs(gh, oh, F, G)
     res = mg.solve(oh, f, mg.Params(), tol=1e-8, maxit=300)
