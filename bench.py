@@ -36,10 +36,10 @@ def dofs(N):
     return 2 * (2 * N - 1) ** 2 + (N + 1) ** 2
 
 
-def ne_pass1_bytes(N):
-    """Algorithmic HBM bytes of one finest-level normal-equation pass 1
-    (t = L^-1 (F - calA x)): read x and F (all unknowns), read Shat^-1 (one
-    per pressure node), write t (all unknowns); 8-byte words, each once."""
+def ne_step_bytes(N):
+    """Algorithmic HBM bytes of one fused normal-equation step on one instance
+    (x <- x + tau L^-1 A L^-1 (F - A x)): read x and F (all unknowns), read
+    Shat^-1 (one per pressure node), write the new x; 8-byte words, each once."""
     n, npres = dofs(N), (N + 1) ** 2
     return 8 * (3 * n + npres)
 
@@ -95,60 +95,70 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1502_04070_amd import Hierarchy, inputs
+    from paper_1502_04070_amd import Batch, Hierarchy, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     F, G = inputs.uniform_f(N_GRID, seed=0)
     Fd = torch.from_numpy(F).cuda()
     Gd = torch.from_numpy(G).cuda()
-    hs = [Hierarchy(N_GRID, b) for b in BETAS]
-    loads = [h.load(Fd, Gd) for h in hs]            # resident load vectors
-    outs = [h.zeros() for h in hs]
+    batch = Batch([N_GRID] * len(BETAS), BETAS)
+    loads = [h.load(Fd, Gd) for h in batch.instances]       # resident load vectors
+    fus = [a for a, _ in loads]
+    gps = [b for _, b in loads]
+    outs = [h.zeros() for h in batch.instances]
+    us = [u for u, _ in outs]
+    ps = [p for _, p in outs]
     torch.cuda.synchronize()
 
     def step(mixed=False):
-        its, per = [], []
-        for h, (fu, gp), (u, p) in zip(hs, loads, outs):
+        for u, p in zip(us, ps):
             u.zero_()
             p.zero_()
-            t0 = time.perf_counter()
-            if mixed:
-                _, _, info = h.solve_mixed(fu, gp, rtol=TOL, maxit=500, u=u, p=p)
-            else:
-                _, _, info = h.solve(fu, gp, rtol=TOL, maxit=500, u=u, p=p)
-            per.append(time.perf_counter() - t0)
-            assert info.status == "ok", info
-            its.append(info.iters)
-        return its, per
+        fn = batch.solve_mixed if mixed else batch.solve
+        _, _, infos = fn(fus, gps, rtol=TOL, maxit=500, us=us, ps=ps)
+        assert all(i.status == "ok" for i in infos), infos
+        return [i.iters for i in infos]
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    all_its, per_beta = [], [0.0] * len(BETAS)
+    all_its = []
     for _ in range(args.steps):
-        its, per = step()
-        all_its.append(its)
-        per_beta = [a + b for a, b in zip(per_beta, per)]
+        all_its.append(step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     cycles = sum(sum(x) for x in all_its)
     value = dofs(N_GRID) * cycles / elapsed
     iters = all_its[-1]
 
-    # FP32 cycles inside FP64 refinement on the same workload
+    # FP32 cycles inside FP64 refinement on the same batch
     step(mixed=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    mixed_its, mixed_per = step(mixed=True)
+    mixed_its = step(mixed=True)
     torch.cuda.synchronize()
     mixed_elapsed = time.perf_counter() - t1
 
-    # dominant kernel: the finest-level normal-equation pass 1, timed with HIP
-    # events on the stream it runs on
-    kern_ms = hs[1].time_kernel(0, reps=args.kernel_reps)
-    kbytes = ne_pass1_bytes(N_GRID)
+    # time to tolerance of each beta solved alone (FP64 and FP32+refinement)
+    tt64, tt32 = {}, {}
+    for b, (fu, gp) in zip(BETAS, loads):
+        h = Hierarchy(N_GRID, b)
+        for mixed, dst in ((False, tt64), (True, tt32)):
+            fn = h.solve_mixed if mixed else h.solve
+            fn(fu, gp, rtol=TOL, maxit=500)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, _, info = fn(fu, gp, rtol=TOL, maxit=500)
+            torch.cuda.synchronize()
+            dst[str(b)] = 1e3 * (time.perf_counter() - ta)
+        del h
+
+    # dominant kernel: the batched finest-level fused normal-equation step,
+    # timed with HIP events on the stream it runs on
+    kern_ms = batch.time_kernel(0, reps=args.kernel_reps)
+    kbytes = ne_step_bytes(N_GRID) * len(BETAS)
     achieved = kbytes / (kern_ms * 1e-3) / 1e9
 
     out = {
@@ -166,18 +176,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "generalized Stokes, unit square, h=1/128 same-diagonal grid, Taylor-Hood "
                                "P2-P1, f iid U[-1,1] (seed 0), g=0, FP64 NE V(2,2) to 1e-8, beta in "
-                               "{0,1,1e2,1e4,1e6}",
-                   "N": N_GRID, "dof": dofs(N_GRID), "betas": BETAS, "levels": hs[0].nlevels},
+                               "{0,1,1e2,1e4,1e6} solved as one batch",
+                   "N": N_GRID, "dof": dofs(N_GRID), "betas": BETAS, "levels": batch[0].nlevels},
         "iterations": dict(zip([str(b) for b in BETAS], iters)),
-        "time_to_tol_ms": dict(zip([str(b) for b in BETAS], [1e3 * t / args.steps for t in per_beta])),
+        "time_to_tol_ms_batch": 1e3 * elapsed / args.steps,
+        "time_to_tol_ms_single": tt64,
         "fp32_refine": {
             "value": dofs(N_GRID) * sum(mixed_its) / mixed_elapsed,
             "iterations": dict(zip([str(b) for b in BETAS], mixed_its)),
-            "time_to_tol_ms": dict(zip([str(b) for b in BETAS], [1e3 * t for t in mixed_per])),
+            "time_to_tol_ms_batch": 1e3 * mixed_elapsed,
+            "time_to_tol_ms_single": tt32,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "finest-level normal-equation pass 1 (k_stencil, M_NE1)",
+            "kernel": "finest-level fused normal-equation step, all 5 instances (k_ne_b<double,16,8>)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -209,6 +209,53 @@ int smg_dot(smg_t h, int level, int which, const double* a, const double* b, dou
             smg_stream_t s);
 
 /*
+ * Batched solves (many independent instances in one set of launches).
+ *
+ * A batch holds n hierarchies built as by smg_setup(N[k], beta[k], prm): the
+ * sizes may differ (each N[k] = n0 * 2^L_k with the common n0), beta is per
+ * instance, the solver parameters are shared (fused path only).  Each iterate
+ * of every instance is computed exactly as by the single-instance solver;
+ * one launch serves every instance taking part in a stage (instances are
+ * aligned by depth below their own finest level), and the whole iterate of
+ * the batch is replayed from one captured HIP graph.  Converged instances are
+ * skipped by their own convergence flag.  Several right-hand sides of one
+ * problem are several instances with the same N and beta.
+ */
+typedef struct smg_batch_s* smg_batch_t;
+
+int smg_batch_setup(int n, const int* N, const double* beta, const smg_params* prm,
+                    smg_batch_t* out);
+int smg_batch_destroy(smg_batch_t b);
+int smg_batch_size(smg_batch_t b);
+/* The hierarchy of instance k (for smg_load, smg_apply, ... on its levels);
+ * owned by the batch.  NULL on a bad index. */
+smg_t smg_batch_handle(smg_batch_t b, int k);
+
+/*
+ * Solve every instance k to ||F_k - calA_k x_k|| <= rtol ||F_k||.  fu, gp, u,
+ * p are HOST arrays of n DEVICE pointers (layouts as for smg_solve of instance
+ * k; u[k], p[k] hold the initial guess and receive the solution).  iters,
+ * relres, status (host arrays of n, may be NULL) receive the per-instance
+ * iterate count, final relative residual and status.  Returns SMG_OK if all
+ * converged, else the largest soft status; synchronous.
+ */
+int smg_batch_solve(smg_batch_t b, const double* const* fu, const double* const* gp, double rtol,
+                    int maxit, double* const* u, double* const* p, int* iters, double* relres,
+                    int* status, smg_stream_t s);
+/* The same with FP32 cycles inside FP64 iterative refinement (see smg_solve_mixed). */
+int smg_batch_solve_mixed(smg_batch_t b, const double* const* fu, const double* const* gp,
+                          double rtol, int maxit, double* const* u, double* const* p, int* iters,
+                          double* relres, int* status, smg_stream_t s);
+
+/*
+ * Batched kernel timing (profiling support): `reps` back-to-back launches of
+ * the finest-level fused normal-equation step of all instances (which = 0),
+ * on the instances' internal work vectors, timed with HIP events on s; mean
+ * milliseconds per launch.  Synchronous.
+ */
+int smg_batch_time_kernel(smg_batch_t b, int which, int reps, double* avg_ms, smg_stream_t s);
+
+/*
  * Kernel timing (profiling support): launches `reps` times, back to back on
  * stream s, one kernel of the finest level on the handle's internal work
  * vectors and returns the mean duration in milliseconds measured with HIP

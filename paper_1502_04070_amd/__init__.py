@@ -4,6 +4,6 @@
 The solver lives in the HIP library libstokesmg.so (C ABI in
 include/stokesmg.h); this package is its thin Python front end.
 """
-from .solver import Hierarchy, SolveInfo  # noqa: F401
+from .solver import Batch, Hierarchy, SolveInfo  # noqa: F401
 
-__all__ = ["Hierarchy", "SolveInfo"]
+__all__ = ["Batch", "Hierarchy", "SolveInfo"]

@@ -55,6 +55,14 @@ SIGNATURES = {
     "smg_solve_mixed": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],
     "smg_dot": [P, I, I, P, P, P, P],
     "smg_time_kernel": [P, I, I, C.POINTER(D), P],
+    "smg_batch_setup": [I, C.POINTER(I), C.POINTER(D), C.POINTER(SmgParams), C.POINTER(P)],
+    "smg_batch_destroy": [P],
+    "smg_batch_size": [P],
+    "smg_batch_time_kernel": [P, I, I, C.POINTER(D), P],
+    "smg_batch_solve": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),
+                        C.POINTER(I), C.POINTER(D), C.POINTER(I), P],
+    "smg_batch_solve_mixed": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),
+                              C.POINTER(I), C.POINTER(D), C.POINTER(I), P],
 }
 
 _lib = None
@@ -74,6 +82,8 @@ def load() -> C.CDLL:
         fn.restype = C.c_int
     lib.smg_last_error.argtypes = []
     lib.smg_last_error.restype = C.c_char_p
+    lib.smg_batch_handle.argtypes = [P, I]
+    lib.smg_batch_handle.restype = P
     _lib = lib
     return lib
 

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -543,8 +544,7 @@ void finish_iter(smg_hier* H, double* ru, double* rp, const int* done, hipStream
   R.mean_partial = H->mpart;
   R.done = done;
   launch_stencil<double>(R, ROWS_UP, s);
-  launch_project_partials(H->mpart, T.ntiles, T.N, T.x.p, done, s);
-  launch_check(T.partial, T.ntiles, H->st, H->hist, s);
+  launch_project_check(H->mpart, T.partial, T.ntiles, T.N, T.x.p, H->st, H->hist, s);
 }
 
 // one FP64 iterate of the solve loop on the internal finest-level vectors
@@ -734,7 +734,9 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     double* s64 = H->alloc<double>(Lv.n_p);
     float* s32 = H->alloc<float>(Lv.n_p);
     Lv.ntiles = stencil_tiles(Lv.N);
-    Lv.partial = H->alloc<double>(Lv.ntiles);
+    // sized for the smallest tile shape, so that batched launches with any
+    // tile shape fit
+    Lv.partial = H->alloc<double>(std::max(Lv.ntiles, stencil_tiles_shape(Lv.N, 8, 8)));
     if (!b64 || !b32 || !s64 || !s32 || !Lv.partial) { delete H; return fail(SMG_ENOMEM, "level %d buffers", l); }
     Vec<double>* v64[3] = {&Lv.x, &Lv.f, &Lv.t};
     Vec<float>* v32[3] = {&Lv.x32, &Lv.f32, &Lv.t32};
@@ -795,8 +797,12 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, H->device);
     const size_t limit = (size_t)std::max(lds_max, lds_optin);
     H->Lc = -1;
+    // largest grid done by the single-workgroup kernel (tuning knob
+    // SMG_COARSE_MAX_N, default 16 squares per side)
+    int cmax = 16;
+    if (const char* ev = std::getenv("SMG_COARSE_MAX_N")) cmax = std::max(0, std::atoi(ev));
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
-      if ((prm.n0 << l) > 16) break;
+      if ((prm.n0 << l) > cmax) break;
       const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));
       if (need > limit) break;
       if (need > 65536 && (coarse_cycle_allow_lds<double>(need) != 0 ||
@@ -806,7 +812,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
       }
       H->Lc = l;
     }
-    if (H->Lc >= 0) {
+    if (H->Lc < 0) H->Lc = 0;   // level 0 alone always fits: its exact solve
+    {
       std::vector<int> ops;
       cc_emit(prm, H->Lc, true, ops);
       H->cc_nops = (int)ops.size();
@@ -817,7 +824,7 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
         return fail(SMG_EHIP, "op list upload");
       }
     }
-    H->mpart = H->alloc<double>(2 * H->lv[L].ntiles);
+    H->mpart = H->alloc<double>(2 * std::max(H->lv[L].ntiles, stencil_tiles_shape(H->lv[L].N, 8, 8)));
     if (!H->mpart) { delete H; return fail(SMG_ENOMEM, "mean partials"); }
   }
   *out = H;
@@ -1031,3 +1038,5 @@ int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t s
 }
 
 }  // extern "C"
+
+#include "smg_batch.inc"

@@ -70,5 +70,36 @@ int coarse_cycle_allow_lds(size_t bytes);
 // p -= mean from partials (sum w p, sum w) pairs of np tiles
 void launch_project_partials(const double* mpart, int np, int N, double* p, const int* done,
                              hipStream_t s);
+// the same, then the convergence test of the solve loop from the np residual
+// partials (done by the last workgroup to finish)
+void launch_project_check(const double* mpart, const double* rpart, int np, int N, double* p,
+                          SolveState* st, double* hist, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// batched launches: many jobs (one per instance and level) in one grid.  A
+// block map entry holds (job << 20) | tile; jobs live in device memory.
+// ---------------------------------------------------------------------------
+constexpr int BMAP_SHIFT = 20;
+inline int bmap(int job, int tile) { return (job << BMAP_SHIFT) | tile; }
+
+template <class T>
+void launch_ne_b(const NEJob<T>* jobs, const int* map, int nb, int tx, bool zg, bool pro,
+                 hipStream_t s);
+template <class T>
+void launch_rr_b(const RRJob<T>* jobs, const int* map, int nb, hipStream_t s);
+template <class T>
+void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s);
+
+// projection + convergence test per job (one job per instance)
+struct PCJob {
+  const double* mpart;
+  const double* rpart;
+  int np, N;
+  double* p;
+  SolveState* st;
+  double* hist;
+};
+__host__ __device__ int pc_blocks(int N);
+void launch_pc_b(const PCJob* jobs, const int* map, int nb, hipStream_t s);
 
 }  // namespace smg

@@ -99,36 +99,46 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   // ---- stage 0: the iterate on the tile plus two squares of halo
   if constexpr (!ZG) {
     if constexpr (PRO) {
-      // one thread per coarse square of the window: 16 fine points each
+      // one work item per (coarse square of the window, component, fine row):
+      // four fine points each
       constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;
       const int Nc = N / 2, Mc = 2 * Nc + 1;
-      for (int e = tid; e < CW * CH; e += NT) {
-        const int ci = e % CW, cj = e / CW;
+      for (int e = tid; e < CW * CH * 8; e += NT) {
+        // fine row slowest, so that a wave mostly shares one row class
+        const int rb = e / (2 * CW * CH), rem = e % (2 * CW * CH);
+        const int c = rem / (CW * CH), cell = rem % (CW * CH);
+        const int ci = cell % CW, cj = cell / CW;
         const int I = i0 / 2 - 1 + ci, Jc = j0 / 2 - 1 + cj;
+        T z[3][3];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          T z[3][3];
+        for (int dB = 0; dB < 3; ++dB)
 #pragma unroll
-          for (int dB = 0; dB < 3; ++dB)
+          for (int dA = 0; dA < 3; ++dA) {
+            const int A = 2 * I + dA, B = 2 * Jc + dB;
+            z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
+                            ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
+          }
+        auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
+        const int b = 4 * Jc + rb;
+        T v[4];
 #pragma unroll
-            for (int dA = 0; dA < 3; ++dA) {
-              const int A = 2 * I + dA, B = 2 * Jc + dB;
-              z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
-                              ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
-            }
-          auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
-          auto IN = [&](int ra, int rb) { return interior(4 * I + ra, 4 * Jc + rb); };
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int ra = 0; ra < 4; ++ra) {
-              const int a = 4 * I + ra, b = 4 * Jc + rb;
-              sx[c][4 * cj + rb][4 * ci + ra] =
-                  interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
-            }
-          auto X = [&](int ra, int rb) -> T& { return sx[c][4 * cj + rb][4 * ci + ra]; };
-          pro_block<T>(X, IN, Z);
+        for (int ra = 0; ra < 4; ++ra) {
+          const int a = 4 * I + ra;
+          v[ra] = interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
         }
+        switch (rb) {
+#define SMG_ROW(RB)                                                              \
+  case RB:                                                                       \
+    if (interior(4 * I + 0, b)) v[0] += pro_w<0, RB, T>(Z);                      \
+    if (interior(4 * I + 1, b)) v[1] += pro_w<1, RB, T>(Z);                      \
+    if (interior(4 * I + 2, b)) v[2] += pro_w<2, RB, T>(Z);                      \
+    if (interior(4 * I + 3, b)) v[3] += pro_w<3, RB, T>(Z);                      \
+    break;
+          SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
+#undef SMG_ROW
+        }
+#pragma unroll
+        for (int ra = 0; ra < 4; ++ra) sx[c][4 * cj + rb][4 * ci + ra] = v[ra];
       }
       for (int e = tid; e < XPW * XPH; e += NT) {
         const int li = e % XPW, lj = e / XPW;
@@ -260,6 +270,31 @@ __global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
   ne_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
+template <class T, int TX, int TY, bool ZG, bool PRO>
+__global__ __launch_bounds__(2 * TX* TY) void k_ne_b(const NEJob<T>* __restrict__ jobs,
+                                                     const int* __restrict__ map) {
+  const int m = map[xcd_remap(blockIdx.x, gridDim.x)];
+  const NEJob<T> J = jobs[m >> BMAP_SHIFT];
+  if (J.done && *J.done) return;
+  ne_tile<T, TX, TY, ZG, PRO>(J, m & ((1 << BMAP_SHIFT) - 1));
+}
+
+template <class T>
+void launch_ne_b(const NEJob<T>* jobs, const int* map, int nb, int tx, bool zg, bool pro,
+                 hipStream_t s) {
+  if (tx == 16) {
+    if (zg) k_ne_b<T, 16, 8, true, false><<<nb, 256, 0, s>>>(jobs, map);
+    else if (pro) k_ne_b<T, 16, 8, false, true><<<nb, 256, 0, s>>>(jobs, map);
+    else k_ne_b<T, 16, 8, false, false><<<nb, 256, 0, s>>>(jobs, map);
+  } else {
+    if (zg) k_ne_b<T, 8, 8, true, false><<<nb, 128, 0, s>>>(jobs, map);
+    else if (pro) k_ne_b<T, 8, 8, false, true><<<nb, 128, 0, s>>>(jobs, map);
+    else k_ne_b<T, 8, 8, false, false><<<nb, 128, 0, s>>>(jobs, map);
+  }
+}
+template void launch_ne_b<double>(const NEJob<double>*, const int*, int, int, bool, bool, hipStream_t);
+template void launch_ne_b<float>(const NEJob<float>*, const int*, int, int, bool, bool, hipStream_t);
+
 TileShape ne_tile_shape(int N) {
   if (N >= 128) return {16, 8};
   return {8, 8};
@@ -388,6 +423,22 @@ __global__ __launch_bounds__(256) void k_resid_restrict(RRJob<T> J) {
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void k_rr_b(const RRJob<T>* __restrict__ jobs,
+                                              const int* __restrict__ map) {
+  const int m = map[xcd_remap(blockIdx.x, gridDim.x)];
+  const RRJob<T> J = jobs[m >> BMAP_SHIFT];
+  if (J.done && *J.done) return;
+  rr_tile<T>(J, m & ((1 << BMAP_SHIFT) - 1));
+}
+
+template <class T>
+void launch_rr_b(const RRJob<T>* jobs, const int* map, int nb, hipStream_t s) {
+  k_rr_b<T><<<nb, 256, 0, s>>>(jobs, map);
+}
+template void launch_rr_b<double>(const RRJob<double>*, const int*, int, hipStream_t);
+template void launch_rr_b<float>(const RRJob<float>*, const int*, int, hipStream_t);
+
+template <class T>
 void launch_resid_restrict(const RRJob<T>& J, hipStream_t s) {
   const int Nc = J.L.N / 2;
   const int nb = ((Nc + 8) / 8) * ((Nc + 8) / 8);
@@ -433,9 +484,31 @@ __device__ __forceinline__ void cc_cell(const LevelCoef<T>& L, const CVec<T>& X,
   cell_apply_acc<T, true, true>(L, UA, PA, y);
 }
 
+// Half of the rows of square (i, j): half 0 -> classes V, H (y[0..3]); half 1
+// -> classes E, D (y[0..3]) and the pressure row (y[4]).
 template <class T>
-__global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
-  if (J.done && *J.done) return;
+__device__ __forceinline__ void cc_half(const LevelCoef<T>& L, const CVec<T>& X, int i, int j, int half,
+                                        T y[5]) {
+  auto PA = [&](int di, int dj) -> T { return X.p(i + di, j + dj); };
+  if (half == 0) {
+    auto U0 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + db); };
+    cell_vel<0, T, true, true>(L, U0, PA, y[0], y[1]);
+    auto U1 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + 1 + da, 2 * j + db); };
+    cell_vel<1, T, true, true>(L, U1, PA, y[2], y[3]);
+    y[4] = T(0);
+  } else {
+    auto U2 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + 1 + db); };
+    cell_vel<2, T, true, true>(L, U2, PA, y[0], y[1]);
+    auto U3 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + 1 + da, 2 * j + 1 + db); };
+    cell_vel<3, T, true, true>(L, U3, PA, y[2], y[3]);
+    auto V0 = [&](int da, int db) -> T { return X.u(0, 2 * i + da, 2 * j + db); };
+    auto V1 = [&](int da, int db) -> T { return X.u(1, 2 * i + da, 2 * j + db); };
+    y[4] = L.h * (SMG_BX_ROW(V0) + SMG_BY_ROW(V1));
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void coarse_body(const CoarseJob<T>& J) {
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -445,7 +518,8 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
     int o = 0;
     for (int l = 0; l <= Lc; ++l) {
       offs[l] = o;
-      o += 3 * clay(n0, l, 0).vlen;
+      const CLay c = clay(n0, l, 0);
+      o += 3 * c.vlen + (c.N + 1) * (c.N + 1);
     }
     offs[Lc + 1] = o;
   }
@@ -453,9 +527,19 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
     const CLay c = clay(n0, l, offs[l]);
     return CVec<T>{sm + c.off + k * c.vlen, c.N, c.Mp, c.NPp};
   };
+  // Shat^-1 of level l, staged next to its three vectors
+  auto sinv_lds = [&](int l) -> const T* {
+    const CLay c = clay(n0, l, offs[l]);
+    return sm + c.off + 3 * c.vlen;
+  };
   // zero everything (padding must be zero), then load F (and X) of level Lc
   for (int e = tid; e < offs[Lc + 1]; e += nt) sm[e] = T(0);
   __syncthreads();
+  for (int l = 0; l <= Lc; ++l) {
+    T* S = const_cast<T*>(sinv_lds(l));
+    const int np = ((n0 << l) + 1) * ((n0 << l) + 1);
+    for (int e = tid; e < np; e += nt) S[e] = J.L[l].sinv[e];
+  }
   {
     const CVec<T> X = vec(Lc, 0), F = vec(Lc, 1);
     const int N = X.N, M = 2 * N + 1, NP = N + 1;
@@ -479,41 +563,49 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
     // the entry level starts from zero only if the caller says so
     const int zg = ((op >> 16) & 1) && (l < Lc || J.zero_guess);
     const LevelCoef<T>& L = J.L[l];
+    const T* Sl = sinv_lds(l);
     const CVec<T> X = vec(l, 0), F = vec(l, 1), Tv = vec(l, 2);
     const int N = X.N, NP = N + 1, ncell = NP * NP;
     auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
     if (kind == CC_NE) {
-      // t = L^-1 (F - A x); x = x + tau L^-1 A t
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        T y[9];
+      // t = L^-1 (F - A x); x = x + tau L^-1 A t.  Two threads per square
+      // (rows V, H and rows E, D, pressure), so that every SIMD has work.
+      for (int e = tid; e < 2 * ncell; e += nt) {
+        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
+        const int i = q % NP, j = q / NP;
+        T y[5];
         if (zg) {
-          for (int q = 0; q < 9; ++q) y[q] = T(0);
+          for (int k2 = 0; k2 < 5; ++k2) y[k2] = T(0);
         } else {
-          cc_cell<T>(L, X, i, j, y);
+          cc_half<T>(L, X, i, j, half, y);
         }
-        for (int cls = 0; cls < 4; ++cls) {
+        for (int k2 = 0; k2 < 2; ++k2) {
+          const int cls = 2 * half + k2;
           const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
           if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = L.adinv[cls] * (F.u(c, a, b) - y[2 * cls + c]);
+          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = L.adinv[cls] * (F.u(c, a, b) - y[2 * k2 + c]);
         }
-        Tv.p(i, j) = L.sinv[e] * (F.p(i, j) - y[8]);
+        if (half) Tv.p(i, j) = Sl[q] * (F.p(i, j) - y[4]);
       }
       __syncthreads();
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        T y[9];
-        cc_cell<T>(L, Tv, i, j, y);
-        for (int cls = 0; cls < 4; ++cls) {
+      for (int e = tid; e < 2 * ncell; e += nt) {
+        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
+        const int i = q % NP, j = q / NP;
+        T y[5];
+        cc_half<T>(L, Tv, i, j, half, y);
+        for (int k2 = 0; k2 < 2; ++k2) {
+          const int cls = 2 * half + k2;
           const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
           if (!interior(a, b)) continue;
           for (int c = 0; c < 2; ++c) {
             const T x0 = zg ? T(0) : X.u(c, a, b);
-            X.u(c, a, b) = x0 + tau * L.adinv[cls] * y[2 * cls + c];
+            X.u(c, a, b) = x0 + tau * L.adinv[cls] * y[2 * k2 + c];
           }
         }
-        const T p0 = zg ? T(0) : X.p(i, j);
-        X.p(i, j) = p0 + tau * L.sinv[e] * y[8];
+        if (half) {
+          const T p0 = zg ? T(0) : X.p(i, j);
+          X.p(i, j) = p0 + tau * Sl[q] * y[4];
+        }
       }
       __syncthreads();
     } else if (kind == CC_UZAWA) {
@@ -542,7 +634,7 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
         auto U0 = [&](int da, int db) -> T { return Tv.u(0, 2 * i + da, 2 * j + db); };
         auto U1 = [&](int da, int db) -> T { return Tv.u(1, 2 * i + da, 2 * j + db); };
         const T bu = L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
-        Tv.p(i, j) = -sigma * L.sinv[e] * (F.p(i, j) - bu);
+        Tv.p(i, j) = -sigma * Sl[e] * (F.p(i, j) - bu);
       }
       __syncthreads();
       // x.u = t.u - tau Ahat^-1 B^T dp ; x.p = p + dp
@@ -572,16 +664,18 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
       __syncthreads();
     } else if (kind == CC_RESTRICT) {
       // T = F - A X on level l, then F_{l-1} = P^T T (and X_{l-1} = 0)
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        T y[9];
-        cc_cell<T>(L, X, i, j, y);
-        for (int cls = 0; cls < 4; ++cls) {
+      for (int e = tid; e < 2 * ncell; e += nt) {
+        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
+        const int i = q % NP, j = q / NP;
+        T y[5];
+        cc_half<T>(L, X, i, j, half, y);
+        for (int k2 = 0; k2 < 2; ++k2) {
+          const int cls = 2 * half + k2;
           const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
           if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = F.u(c, a, b) - y[2 * cls + c];
+          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = F.u(c, a, b) - y[2 * k2 + c];
         }
-        Tv.p(i, j) = F.p(i, j) - y[8];
+        if (half) Tv.p(i, j) = F.p(i, j) - y[4];
       }
       __syncthreads();
       const CVec<T> Fc = vec(l - 1, 1), Xc = vec(l - 1, 0);
@@ -684,11 +778,31 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
+  if (J.done && *J.done) return;
+  coarse_body<T>(J);
+}
+
+template <class T>
+__global__ __launch_bounds__(512) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
+  const CoarseJob<T>& J = jobs[blockIdx.x];
+  if (J.done && *J.done) return;
+  coarse_body<T>(J);
+}
+
+template <class T>
+void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s) {
+  k_coarse_cycle_b<T><<<njobs, 512, lds, s>>>(jobs);
+}
+template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, hipStream_t);
+template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, hipStream_t);
+
 size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
   size_t tot = 0;
   for (int l = 0; l <= Lc; ++l) {
     const size_t N = (size_t)n0 << l, Mp = 2 * N + 5, NPp = N + 3;
-    tot += 3 * (2 * Mp * Mp + NPp * NPp);
+    tot += 3 * (2 * Mp * Mp + NPp * NPp) + (N + 1) * (N + 1);
   }
   return tot * elem;
 }
@@ -704,8 +818,11 @@ template int launch_coarse_cycle<float>(const CoarseJob<float>&, hipStream_t);
 
 template <class T>
 int coarse_cycle_allow_lds(size_t bytes) {
-  return (int)hipFuncSetAttribute((const void*)k_coarse_cycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
+  int e1 = (int)hipFuncSetAttribute((const void*)k_coarse_cycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)bytes);
+  int e2 = (int)hipFuncSetAttribute((const void*)k_coarse_cycle_b<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e1 != 0 ? e1 : e2;
 }
 template int coarse_cycle_allow_lds<double>(size_t);
 template int coarse_cycle_allow_lds<float>(size_t);
@@ -743,6 +860,84 @@ void launch_project_partials(const double* mpart, int np, int N, double* p, cons
                              hipStream_t s) {
   const int n = (N + 1) * (N + 1);
   k_project_partials<<<(n + 1023) / 1024, 256, 0, s>>>(mpart, np, N, p, done);
+}
+
+// Mean projection by every workgroup, then the convergence test by the last
+// workgroup to finish (it is last, so every other workgroup has already read
+// the flag it is about to set).  The residual pieces are reduced in a fixed
+// order, so the test is deterministic.
+__device__ __forceinline__ void project_check_body(const double* __restrict__ mpart,
+                                                   const double* __restrict__ rpart, int np, int N,
+                                                   double* p, SolveState* st, double* hist, int blk,
+                                                   int nblk) {
+  __shared__ double red[4];
+  __shared__ double sh_mean;
+  __shared__ int sh_last;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) {
+    s1 += mpart[2 * k];
+    s2 += mpart[2 * k + 1];
+  }
+  const double t1 = wg_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = wg_sum<256>(s2, red);
+  if (threadIdx.x == 0) sh_mean = t1 / t2;
+  __syncthreads();
+  const int n = (N + 1) * (N + 1);
+  const double m = sh_mean;
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk * 1024 + k * 256 + threadIdx.x;
+    if (e < n) p[e] -= m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned ticket = atomicAdd(&st->arrive, 1u);
+    sh_last = (ticket == (unsigned)nblk - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!sh_last) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) s += rpart[k];
+  const double r2 = wg_sum<256>(s, red);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(r2 / st->fnorm2);
+    const int it = st->iters + 1;
+    st->relres = rel;
+    st->iters = it;
+    if (hist) hist[it - 1] = rel;
+    st->arrive = 0u;
+    if (!(rel == rel) || rel > 1e300) st->done = 3;
+    else if (r2 <= st->tol2 * st->fnorm2) st->done = 1;
+    else if (rel > 1e6) st->done = 2;
+    else if (it >= st->maxit) st->done = 4;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_project_check(const double* __restrict__ mpart,
+                                                       const double* __restrict__ rpart, int np, int N,
+                                                       double* p, SolveState* st, double* hist) {
+  if (st->done) return;
+  project_check_body(mpart, rpart, np, N, p, st, hist, blockIdx.x, gridDim.x);
+}
+
+__host__ __device__ int pc_blocks(int N) { return ((N + 1) * (N + 1) + 1023) / 1024; }
+
+void launch_project_check(const double* mpart, const double* rpart, int np, int N, double* p,
+                          SolveState* st, double* hist, hipStream_t s) {
+  k_project_check<<<pc_blocks(N), 256, 0, s>>>(mpart, rpart, np, N, p, st, hist);
+}
+
+__global__ __launch_bounds__(256) void k_pc_b(const PCJob* __restrict__ jobs, const int* __restrict__ map) {
+  const int m = map[blockIdx.x];
+  const PCJob J = jobs[m >> BMAP_SHIFT];
+  if (J.st->done) return;
+  project_check_body(J.mpart, J.rpart, J.np, J.N, J.p, J.st, J.hist, m & ((1 << BMAP_SHIFT) - 1),
+                     pc_blocks(J.N));
+}
+
+void launch_pc_b(const PCJob* jobs, const int* map, int nb, hipStream_t s) {
+  k_pc_b<<<nb, 256, 0, s>>>(jobs, map);
 }
 
 }  // namespace smg

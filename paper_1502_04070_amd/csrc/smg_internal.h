@@ -52,6 +52,38 @@ int stencil_tiles(int N);
 
 template <class T>
 void launch_stencil(const StencilJob<T>& J, int rows, hipStream_t s);
+// operation flags of a job (the compile-time mode of the stencil kernel)
+template <class T>
+unsigned stencil_flags(const StencilJob<T>& J, int rows);
+// batched: jobs with identical flags, one tile shape (tx, ty) for all
+template <class T>
+void launch_stencil_b(const StencilJob<T>* jobs, const int* map, int nb, int tx, int ty,
+                      unsigned flags, hipStream_t s);
+int stencil_tiles_shape(int N, int tx, int ty);
+
+// batched prolongation (one job per instance)
+template <class T>
+struct ProJob {
+  int Nc;
+  const T* zu;
+  const T* zp;
+  T* u;
+  T* p;
+  const int* done;
+};
+int prolong_tiles(int Nc);
+template <class T>
+void launch_prolong_b(const ProJob<T>* jobs, const int* map, int nb, hipStream_t s);
+
+// batched elementwise: cast d -> f (mode 0), d += f (mode 1), d = 0 (mode 2)
+struct EwJob {
+  double* d;
+  float* f;
+  int64_t n;
+  const int* done;
+};
+int ew_tiles(int64_t n);
+void launch_ew_b(const EwJob* jobs, const int* map, int nb, int mode, hipStream_t s);
 
 // r_c = P^T r_f (velocity P2, pressure P1); also zero (xcu, xcp) if not NULL.
 template <class T>
@@ -96,6 +128,8 @@ struct SolveState {
   double fnorm2;   // ||F||^2
   double tol2;     // rtol^2
   double relres;   // last relative residual
+  unsigned arrive; // workgroups of k_project_check that have finished (reset by the last)
+  unsigned pad2;
 };
 // reduce `np` partials to ||r||^2; record the iterate: iters++, history, done flags.
 void launch_check(const double* partials, int np, SolveState* st, double* hist, hipStream_t s);

@@ -264,9 +264,17 @@ constexpr unsigned M_UZ2 = F_ROWS_P | F_IN_U | F_RHS_P | F_DIAG_P | F_OUT_P;
 constexpr unsigned M_UZ3 = RW_UP | F_IN_P | F_RHS_P | F_BASE_U | F_BASE_P | F_DIAG_U | OUT_UP;
 constexpr unsigned M_UZ3Z = RW_UP | F_IN_P | F_RHS_P | F_BASE_U | F_DIAG_U | OUT_UP;
 constexpr unsigned M_MASK_U = F_ROWS_U | F_RHS_U | F_OUT_U;
+constexpr unsigned M_COPY = RW_UP | F_RHS_U | F_RHS_P | OUT_UP;
+constexpr unsigned M_ZERO = RW_UP | OUT_UP;
 
 template <class T>
+unsigned stencil_flags(const StencilJob<T>& J, int rows);
+template <class T>
 unsigned job_flags(const StencilJob<T>& J, int rows) {
+  return stencil_flags<T>(J, rows);
+}
+template <class T>
+unsigned stencil_flags(const StencilJob<T>& J, int rows) {
   unsigned f = 0;
   if (rows & ROWS_U) f |= F_ROWS_U;
   if (rows & ROWS_P) f |= F_ROWS_P;
@@ -297,7 +305,7 @@ static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s
     SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
     SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
     SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
-    SMG_CASE(M_MASK_U)
+    SMG_CASE(M_MASK_U) SMG_CASE(M_COPY) SMG_CASE(M_ZERO)
     default: break;
   }
 #undef SMG_CASE
@@ -321,6 +329,47 @@ void launch_stencil(const StencilJob<T>& J, int rows, hipStream_t s) {
 }
 template void launch_stencil<double>(const StencilJob<double>&, int, hipStream_t);
 template void launch_stencil<float>(const StencilJob<float>&, int, hipStream_t);
+template unsigned stencil_flags<double>(const StencilJob<double>&, int);
+template unsigned stencil_flags<float>(const StencilJob<float>&, int);
+
+int stencil_tiles_shape(int N, int tx, int ty) { return ((N + tx) / tx) * ((N + ty) / ty); }
+
+template <class T, int TX, int TY, unsigned F>
+__global__ __launch_bounds__(TX* TY) void k_stencil_b(const StencilJob<T>* __restrict__ jobs,
+                                                     const int* __restrict__ map) {
+  const int m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
+  const StencilJob<T> J = jobs[m >> 20];
+  if (J.done && *J.done) return;
+  stencil_tile<T, TX, TY, F>(J, m & ((1 << 20) - 1));
+}
+
+template <class T, int TX, int TY>
+static void launch_stencil_b_shape(const StencilJob<T>* jobs, const int* map, int nb, unsigned f,
+                                   hipStream_t s) {
+#define SMG_CASE(MODE) \
+  case MODE: k_stencil_b<T, TX, TY, MODE><<<nb, TX * TY, 0, s>>>(jobs, map); return;
+  switch (f) {
+    SMG_CASE(M_APPLY) SMG_CASE(M_RESID) SMG_CASE(M_RESID_NORM) SMG_CASE(M_RESID_BOTH)
+    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
+    SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
+    SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
+    SMG_CASE(M_MASK_U) SMG_CASE(M_COPY) SMG_CASE(M_ZERO)
+    default: k_stencil_b<T, TX, TY, 0u><<<nb, TX * TY, 0, s>>>(jobs, map); return;
+  }
+#undef SMG_CASE
+}
+
+template <class T>
+void launch_stencil_b(const StencilJob<T>* jobs, const int* map, int nb, int tx, int ty,
+                      unsigned flags, hipStream_t s) {
+  if (tx == 16 && ty == 16) launch_stencil_b_shape<T, 16, 16>(jobs, map, nb, flags, s);
+  else if (tx == 16 && ty == 8) launch_stencil_b_shape<T, 16, 8>(jobs, map, nb, flags, s);
+  else launch_stencil_b_shape<T, 8, 8>(jobs, map, nb, flags, s);
+}
+template void launch_stencil_b<double>(const StencilJob<double>*, const int*, int, int, int, unsigned,
+                                       hipStream_t);
+template void launch_stencil_b<float>(const StencilJob<float>*, const int*, int, int, int, unsigned,
+                                      hipStream_t);
 
 // ---------------------------------------------------------------------------
 // transfers (Section 3): one thread per coarse square
@@ -409,12 +458,10 @@ __device__ __forceinline__ void pro_point(int Nf, int I, int J, FZ Z, T* uf) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict__ zu,
-                                                     const T* __restrict__ zp, T* u, T* p,
-                                                     const int* done) {
-  if (done && *done) return;
-  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+__device__ __forceinline__ void prolong_body(int Nc, const T* __restrict__ zu, const T* __restrict__ zp,
+                                             T* u, T* p, int bx, int by) {
+  const int I = bx * 16 + (threadIdx.x & 15);
+  const int J = by * 16 + (threadIdx.x >> 4);
   if (I > Nc || J > Nc) return;
   const int Nf = 2 * Nc, Mc = 2 * Nc + 1, Mf = 2 * Nf + 1;
 #pragma unroll
@@ -443,6 +490,33 @@ __global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict
   if (J < Nc) p[(size_t)(fj + 1) * NPf + fi] += T(0.5) * (Zp(I, J) + Zp(I, J + 1));
   if (I < Nc && J < Nc) p[(size_t)(fj + 1) * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J + 1));
 }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict__ zu,
+                                                     const T* __restrict__ zp, T* u, T* p,
+                                                     const int* done) {
+  if (done && *done) return;
+  prolong_body<T>(Nc, zu, zp, u, p, blockIdx.x, blockIdx.y);
+}
+
+int prolong_tiles(int Nc) { return ((Nc + 16) / 16) * ((Nc + 16) / 16); }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_b(const ProJob<T>* __restrict__ jobs,
+                                                   const int* __restrict__ map) {
+  const int m = map[blockIdx.x];
+  const ProJob<T> J = jobs[m >> 20];
+  if (J.done && *J.done) return;
+  const int tile = m & ((1 << 20) - 1), ntx = (J.Nc + 16) / 16;
+  prolong_body<T>(J.Nc, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
+}
+
+template <class T>
+void launch_prolong_b(const ProJob<T>* jobs, const int* map, int nb, hipStream_t s) {
+  k_prolong_b<T><<<nb, 256, 0, s>>>(jobs, map);
+}
+template void launch_prolong_b<double>(const ProJob<double>*, const int*, int, hipStream_t);
+template void launch_prolong_b<float>(const ProJob<float>*, const int*, int, hipStream_t);
 
 template <class T>
 void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
@@ -810,6 +884,27 @@ __global__ __launch_bounds__(256) void k_axpy_f32(double* x, const float* __rest
 }
 void launch_axpy_f32(double* x, const float* d, int64_t n, const int* done, hipStream_t s) {
   k_axpy_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, d, n, done);
+}
+
+int ew_tiles(int64_t n) { return (int)((n + 1023) / 1024); }
+
+__global__ __launch_bounds__(256) void k_ew_b(const EwJob* __restrict__ jobs, const int* __restrict__ map,
+                                              int mode) {
+  const int m = map[blockIdx.x];
+  const EwJob J = jobs[m >> 20];
+  if (J.done && *J.done) return;
+  const int64_t base = (int64_t)(m & ((1 << 20) - 1)) * 1024;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t e = base + k * 256 + threadIdx.x;
+    if (e >= J.n) break;
+    if (mode == 0) J.f[e] = (float)J.d[e];
+    else if (mode == 1) J.d[e] += (double)J.f[e];
+    else J.d[e] = 0.0;
+  }
+}
+
+void launch_ew_b(const EwJob* jobs, const int* map, int nb, int mode, hipStream_t s) {
+  k_ew_b<<<nb, 256, 0, s>>>(jobs, map, mode);
 }
 
 }  // namespace smg

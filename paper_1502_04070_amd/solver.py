@@ -58,12 +58,24 @@ class Hierarchy:
             _lib.check(self.lib.smg_setup(self.N, self.beta, C.byref(self.params), C.byref(h)),
                        "smg_setup")
         self.h = h
+        self._owned = True
         self.nlevels = self.lib.smg_num_levels(h)
         self.L = self.nlevels - 1
 
+    @classmethod
+    def _view(cls, lib, handle, params, N, beta, smoother, device):
+        """A non-owning front end for a hierarchy that belongs to a batch."""
+        self = cls.__new__(cls)
+        self.lib, self.h, self.params = lib, C.c_void_p(handle), params
+        self.N, self.beta, self.smoother, self.device = N, beta, smoother, device
+        self._owned = False
+        self.nlevels = lib.smg_num_levels(self.h)
+        self.L = self.nlevels - 1
+        return self
+
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if getattr(self, "_owned", True) and h is not None and h.value:
             self.lib.smg_destroy(h)
             self.h = None
 
@@ -226,3 +238,72 @@ class Hierarchy:
     def solve_mixed(self, fu, gp, rtol=1e-10, maxit=400, u=None, p=None):
         """FP32 cycles inside FP64 iterative refinement."""
         return self._solve(self.lib.smg_solve_mixed, "smg_solve_mixed", fu, gp, rtol, maxit, u, p)
+
+
+class Batch:
+    """Many independent instances (sizes N_k = n0 2^L_k, coefficients beta_k)
+    solved together: one launch per stage for all of them, one captured graph
+    per iterate.  Several right-hand sides of one problem are several
+    instances with equal (N, beta)."""
+
+    def __init__(self, Ns, betas, smoother: str = "ne", tau: float | None = None, sigma: float = 0.8,
+                 nu_pre: int = 2, nu_post: int = 2, gamma: int = 1, n0: int = 2):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP solver needs a GPU")
+        if len(Ns) != len(betas):
+            raise ValueError("Ns and betas differ in length")
+        if tau is None:
+            tau = 0.35 if smoother == "ne" else 0.8
+        self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma), int(nu_pre),
+                                     int(nu_post), int(gamma), int(n0), 0)
+        n = len(Ns)
+        Na = (C.c_int * n)(*[int(v) for v in Ns])
+        Ba = (C.c_double * n)(*[float(v) for v in betas])
+        b = C.c_void_p()
+        _lib.check(self.lib.smg_batch_setup(n, Na, Ba, C.byref(self.params), C.byref(b)), "smg_batch_setup")
+        self.b = b
+        self.n = n
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.instances = [Hierarchy._view(self.lib, self.lib.smg_batch_handle(b, k), self.params, int(Ns[k]),
+                                          float(betas[k]), smoother, dev) for k in range(n)]
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, k) -> Hierarchy:
+        return self.instances[k]
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value:
+            self.lib.smg_batch_destroy(b)
+            self.b = None
+
+    def _solve(self, fn, name, fus, gps, rtol, maxit, us, ps):
+        n = self.n
+        if us is None:
+            us, ps = zip(*[h.zeros() for h in self.instances])
+        for k, h in enumerate(self.instances):
+            h._chk(h.L, (fus[k], "u"), (gps[k], "p"), (us[k], "u"), (ps[k], "p"))
+        arr = lambda ts: (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        it = (C.c_int * n)()
+        rel = (C.c_double * n)()
+        st = (C.c_int * n)()
+        code = fn(self.b, arr(fus), arr(gps), float(rtol), int(maxit), arr(us), arr(ps), it, rel, st, _stream())
+        _lib.check(code, name, soft_ok=True)
+        infos = [SolveInfo(_lib.STATUS[st[k]], it[k], rel[k], []) for k in range(n)]
+        return list(us), list(ps), infos
+
+    def time_kernel(self, which: int = 0, reps: int = 50) -> float:
+        """Mean duration (ms) of one batched finest-level fused NE step launch."""
+        ms = C.c_double()
+        _lib.check(self.lib.smg_batch_time_kernel(self.b, int(which), int(reps), C.byref(ms), _stream()),
+                   "smg_batch_time_kernel")
+        return ms.value
+
+    def solve(self, fus, gps, rtol=1e-8, maxit=200, us=None, ps=None):
+        return self._solve(self.lib.smg_batch_solve, "smg_batch_solve", fus, gps, rtol, maxit, us, ps)
+
+    def solve_mixed(self, fus, gps, rtol=1e-10, maxit=400, us=None, ps=None):
+        return self._solve(self.lib.smg_batch_solve_mixed, "smg_batch_solve_mixed", fus, gps, rtol, maxit, us, ps)
