@@ -162,6 +162,10 @@ int smg_coarse_solve(smg_t h, const double* ru, const double* rp, double* zu, do
  * representative of P_k (Section 1 fixes int p = 0). */
 int smg_project_mean(smg_t h, int level, double* p, smg_stream_t s);
 
+/* v <- v - m (sum_i v_i) / (sum_i m_i): the transpose of smg_project_mean
+ * (maps any pressure cotangent to a compatible adjoint right-hand side). */
+int smg_project_dual(smg_t h, int level, double* v, smg_stream_t s);
+
 /* One iterate of Section 3 on the finest level (nu_pre smoothing steps,
  * coarse-grid correction by gamma recursive iterates, nu_post steps),
  * followed by the mean projection; in place on (u, p). */

@@ -49,6 +49,7 @@ SIGNATURES = {
     "smg_prolong_add": [P, I, P, P, P, P, P],
     "smg_coarse_solve": [P, P, P, P, P, P],
     "smg_project_mean": [P, I, P, P],
+    "smg_project_dual": [P, I, P, P],
     "smg_cycle": [P, P, P, P, P, P],
     "smg_cycle_f32": [P, P, P, P, P, P],
     "smg_solve": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],

@@ -959,6 +959,14 @@ int smg_project_mean(smg_t h, int level, double* p, smg_stream_t sv) {
   return launch_status("smg_project_mean");
 }
 
+int smg_project_dual(smg_t h, int level, double* v, smg_stream_t sv) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!v) return fail(SMG_EINVAL, "null vector");
+  launch_project_dual(h->lv[level].N, v, h->red, (hipStream_t)sv);
+  return launch_status("smg_project_dual");
+}
+
 int smg_cycle(smg_t h, const double* fu, const double* gp, double* u, double* p, smg_stream_t sv) {
   int rc = check_level(h, 0);
   if (rc) return rc;

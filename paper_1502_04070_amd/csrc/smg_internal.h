@@ -101,6 +101,8 @@ void launch_coarse_solve(int N0, int nc, const double* cinv, const T* ru, const 
 // p <- p - (m . p) / sum(m); uses `partials` (>= mean_blocks(N) doubles x 2)
 int mean_blocks(int N);
 void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s);
+// v <- v - m (sum_i v_i) / (sum_i m_i): the transpose of the mean projection
+void launch_project_dual(int N, double* p, double* partials, hipStream_t s);
 
 // Shat^-1 at setup
 template <class T>

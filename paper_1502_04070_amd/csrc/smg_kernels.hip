@@ -600,8 +600,10 @@ int mean_blocks(int N) {
   return (n + 256 * MEAN_PER_THREAD - 1) / (256 * MEAN_PER_THREAD);
 }
 
+// mode 0: p <- p - (sum w p / sum w)          (mean projection)
+// mode 1: p <- p - w (sum p / sum w)          (its transpose, Pi^T)
 __global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __restrict__ p,
-                                                      double* partials, const int* done) {
+                                                      double* partials, const int* done, int mode) {
   if (done && *done) return;
   __shared__ double red[4];
   const int n = (N + 1) * (N + 1);
@@ -610,7 +612,7 @@ __global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __res
     const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
     if (e < n) {
       const double w = p1_weight(N, e % (N + 1), e / (N + 1));
-      s1 += w * p[e];
+      s1 += (mode == 0 ? w : 1.0) * p[e];
       s2 += w;
     }
   }
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __res
 }
 
 __global__ __launch_bounds__(256) void k_mean_apply(int N, double* p, const double* __restrict__ partials,
-                                                    int nparts, const int* done) {
+                                                    int nparts, const int* done, int mode) {
   if (done && *done) return;
   __shared__ double red[4];
   __shared__ double mean;
@@ -641,14 +643,20 @@ __global__ __launch_bounds__(256) void k_mean_apply(int N, double* p, const doub
   const int n = (N + 1) * (N + 1);
   for (int k = 0; k < MEAN_PER_THREAD; ++k) {
     const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
-    if (e < n) p[e] -= mean;
+    if (e < n) p[e] -= (mode == 0 ? 1.0 : p1_weight(N, e % (N + 1), e / (N + 1))) * mean;
   }
 }
 
 void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s) {
   const int nb = mean_blocks(N);
-  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, done);
-  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, done);
+  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, done, 0);
+  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, done, 0);
+}
+
+void launch_project_dual(int N, double* p, double* partials, hipStream_t s) {
+  const int nb = mean_blocks(N);
+  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, nullptr, 1);
+  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, nullptr, 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -190,6 +190,13 @@ class Hierarchy:
         _lib.check(self.lib.smg_project_mean(self.h, level, _ptr(p), _stream()), "smg_project_mean")
         return p
 
+    def project_dual(self, v, level=None):
+        """In place: v <- v - m (sum v) / (sum m), the transpose of project_mean."""
+        level = self.L if level is None else level
+        self._chk(level, (v, "p"))
+        _lib.check(self.lib.smg_project_dual(self.h, level, _ptr(v), _stream()), "smg_project_dual")
+        return v
+
     def dot(self, a, b, which, level=None):
         level = self.L if level is None else level
         self._chk(level, (a, "u" if which == 0 else "p"), (b, "u" if which == 0 else "p"))
