@@ -448,335 +448,7 @@ template void launch_resid_restrict<double>(const RRJob<double>&, hipStream_t);
 template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// k_coarse_cycle: the iterate on levels 0..Lc in one workgroup, all in LDS
-// ---------------------------------------------------------------------------
-// Per level l the LDS holds three vectors X, F, T; a vector is a velocity
-// lattice padded by two points on every side, (2N+5)^2 per component, then a
-// pressure lattice padded by one vertex, (N+3)^2, all zero outside the interior.
-
-struct CLay {
-  int N, Mp, NPp, vlen;  // padded sizes
-  int off;               // offset of X of this level in the LDS array (F, T follow)
-};
-
-__device__ __forceinline__ CLay clay(int n0, int l, int base_off) {
-  CLay c;
-  c.N = n0 << l;
-  c.Mp = 2 * c.N + 5;
-  c.NPp = c.N + 3;
-  c.vlen = 2 * c.Mp * c.Mp + c.NPp * c.NPp;
-  c.off = base_off;
-  return c;
-}
-
-template <class T>
-struct CVec {
-  T* v;
-  int N, Mp, NPp;
-  __device__ __forceinline__ T& u(int c, int a, int b) const { return v[(c * Mp + b + 2) * Mp + a + 2]; }
-  __device__ __forceinline__ T& p(int i, int j) const { return v[2 * Mp * Mp + (j + 1) * NPp + i + 1]; }
-};
-
-template <class T>
-__device__ __forceinline__ void cc_cell(const LevelCoef<T>& L, const CVec<T>& X, int i, int j, T y[9]) {
-  auto UA = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + db); };
-  auto PA = [&](int di, int dj) -> T { return X.p(i + di, j + dj); };
-  cell_apply_acc<T, true, true>(L, UA, PA, y);
-}
-
-// Half of the rows of square (i, j): half 0 -> classes V, H (y[0..3]); half 1
-// -> classes E, D (y[0..3]) and the pressure row (y[4]).
-template <class T>
-__device__ __forceinline__ void cc_half(const LevelCoef<T>& L, const CVec<T>& X, int i, int j, int half,
-                                        T y[5]) {
-  auto PA = [&](int di, int dj) -> T { return X.p(i + di, j + dj); };
-  if (half == 0) {
-    auto U0 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + db); };
-    cell_vel<0, T, true, true>(L, U0, PA, y[0], y[1]);
-    auto U1 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + 1 + da, 2 * j + db); };
-    cell_vel<1, T, true, true>(L, U1, PA, y[2], y[3]);
-    y[4] = T(0);
-  } else {
-    auto U2 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + da, 2 * j + 1 + db); };
-    cell_vel<2, T, true, true>(L, U2, PA, y[0], y[1]);
-    auto U3 = [&](int c, int da, int db) -> T { return X.u(c, 2 * i + 1 + da, 2 * j + 1 + db); };
-    cell_vel<3, T, true, true>(L, U3, PA, y[2], y[3]);
-    auto V0 = [&](int da, int db) -> T { return X.u(0, 2 * i + da, 2 * j + db); };
-    auto V1 = [&](int da, int db) -> T { return X.u(1, 2 * i + da, 2 * j + db); };
-    y[4] = L.h * (SMG_BX_ROW(V0) + SMG_BY_ROW(V1));
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void coarse_body(const CoarseJob<T>& J) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int Lc = J.Lc, n0 = J.n0;
-  int offs[CC_MAX_LEVELS + 2];
-  {
-    int o = 0;
-    for (int l = 0; l <= Lc; ++l) {
-      offs[l] = o;
-      const CLay c = clay(n0, l, 0);
-      o += 3 * c.vlen + (c.N + 1) * (c.N + 1);
-    }
-    offs[Lc + 1] = o;
-  }
-  auto vec = [&](int l, int k) -> CVec<T> {
-    const CLay c = clay(n0, l, offs[l]);
-    return CVec<T>{sm + c.off + k * c.vlen, c.N, c.Mp, c.NPp};
-  };
-  // Shat^-1 of level l, staged next to its three vectors
-  auto sinv_lds = [&](int l) -> const T* {
-    const CLay c = clay(n0, l, offs[l]);
-    return sm + c.off + 3 * c.vlen;
-  };
-  // zero everything (padding must be zero), then load F (and X) of level Lc
-  for (int e = tid; e < offs[Lc + 1]; e += nt) sm[e] = T(0);
-  __syncthreads();
-  for (int l = 0; l <= Lc; ++l) {
-    T* S = const_cast<T*>(sinv_lds(l));
-    const int np = ((n0 << l) + 1) * ((n0 << l) + 1);
-    for (int e = tid; e < np; e += nt) S[e] = J.L[l].sinv[e];
-  }
-  {
-    const CVec<T> X = vec(Lc, 0), F = vec(Lc, 1);
-    const int N = X.N, M = 2 * N + 1, NP = N + 1;
-    for (int e = tid; e < 2 * M * M; e += nt) {
-      const int c = e / (M * M), q = e % (M * M), a = q % M, b = q / M;
-      if (a > 0 && a < 2 * N && b > 0 && b < 2 * N) {
-        F.u(c, a, b) = J.fu[e];
-        if (!J.zero_guess) X.u(c, a, b) = J.xu[e];
-      }
-    }
-    for (int e = tid; e < NP * NP; e += nt) {
-      F.p(e % NP, e / NP) = J.fp[e];
-      if (!J.zero_guess) X.p(e % NP, e / NP) = J.xp[e];
-    }
-  }
-  __syncthreads();
-  const T tau = J.tau, sigma = J.sigma;
-  for (int k = 0; k < J.nops; ++k) {
-    const int op = J.ops[k];
-    const int kind = op & 0xff, l = (op >> 8) & 0xff;
-    // the entry level starts from zero only if the caller says so
-    const int zg = ((op >> 16) & 1) && (l < Lc || J.zero_guess);
-    const LevelCoef<T>& L = J.L[l];
-    const T* Sl = sinv_lds(l);
-    const CVec<T> X = vec(l, 0), F = vec(l, 1), Tv = vec(l, 2);
-    const int N = X.N, NP = N + 1, ncell = NP * NP;
-    auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
-    if (kind == CC_NE) {
-      // t = L^-1 (F - A x); x = x + tau L^-1 A t.  Two threads per square
-      // (rows V, H and rows E, D, pressure), so that every SIMD has work.
-      for (int e = tid; e < 2 * ncell; e += nt) {
-        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
-        const int i = q % NP, j = q / NP;
-        T y[5];
-        if (zg) {
-          for (int k2 = 0; k2 < 5; ++k2) y[k2] = T(0);
-        } else {
-          cc_half<T>(L, X, i, j, half, y);
-        }
-        for (int k2 = 0; k2 < 2; ++k2) {
-          const int cls = 2 * half + k2;
-          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
-          if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = L.adinv[cls] * (F.u(c, a, b) - y[2 * k2 + c]);
-        }
-        if (half) Tv.p(i, j) = Sl[q] * (F.p(i, j) - y[4]);
-      }
-      __syncthreads();
-      for (int e = tid; e < 2 * ncell; e += nt) {
-        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
-        const int i = q % NP, j = q / NP;
-        T y[5];
-        cc_half<T>(L, Tv, i, j, half, y);
-        for (int k2 = 0; k2 < 2; ++k2) {
-          const int cls = 2 * half + k2;
-          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
-          if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) {
-            const T x0 = zg ? T(0) : X.u(c, a, b);
-            X.u(c, a, b) = x0 + tau * L.adinv[cls] * y[2 * k2 + c];
-          }
-        }
-        if (half) {
-          const T p0 = zg ? T(0) : X.p(i, j);
-          X.p(i, j) = p0 + tau * Sl[q] * y[4];
-        }
-      }
-      __syncthreads();
-    } else if (kind == CC_UZAWA) {
-      // t.u = u + tau Ahat^-1 (f - A u - B^T p)
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        T y[9];
-        if (zg) {
-          for (int q = 0; q < 9; ++q) y[q] = T(0);
-        } else {
-          cc_cell<T>(L, X, i, j, y);
-        }
-        for (int cls = 0; cls < 4; ++cls) {
-          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
-          if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) {
-            const T x0 = zg ? T(0) : X.u(c, a, b);
-            Tv.u(c, a, b) = x0 + tau * L.adinv[cls] * (F.u(c, a, b) - y[2 * cls + c]);
-          }
-        }
-      }
-      __syncthreads();
-      // t.p = dp = -sigma Shat^-1 (g - B t.u)
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        auto U0 = [&](int da, int db) -> T { return Tv.u(0, 2 * i + da, 2 * j + db); };
-        auto U1 = [&](int da, int db) -> T { return Tv.u(1, 2 * i + da, 2 * j + db); };
-        const T bu = L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
-        Tv.p(i, j) = -sigma * Sl[e] * (F.p(i, j) - bu);
-      }
-      __syncthreads();
-      // x.u = t.u - tau Ahat^-1 B^T dp ; x.p = p + dp
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP;
-        auto PA = [&](int di, int dj) -> T { return Tv.p(i + di, j + dj); };
-        for (int cls = 1; cls < 4; ++cls) {
-          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
-          if (!interior(a, b)) continue;
-          T bx, by;
-          if (cls == 1) { bx = cell_btx<1, T>(PA); by = cell_bty<1, T>(PA); }
-          else if (cls == 2) { bx = cell_btx<2, T>(PA); by = cell_bty<2, T>(PA); }
-          else { bx = cell_btx<3, T>(PA); by = cell_bty<3, T>(PA); }
-          X.u(0, a, b) = Tv.u(0, a, b) - tau * L.adinv[cls] * L.h * bx;
-          X.u(1, a, b) = Tv.u(1, a, b) - tau * L.adinv[cls] * L.h * by;
-        }
-        {
-          const int a = 2 * i, b = 2 * j;   // vertex nodes: no pressure coupling
-          if (interior(a, b)) {
-            X.u(0, a, b) = Tv.u(0, a, b);
-            X.u(1, a, b) = Tv.u(1, a, b);
-          }
-        }
-        const T p0 = zg ? T(0) : X.p(i, j);
-        X.p(i, j) = p0 + Tv.p(i, j);
-      }
-      __syncthreads();
-    } else if (kind == CC_RESTRICT) {
-      // T = F - A X on level l, then F_{l-1} = P^T T (and X_{l-1} = 0)
-      for (int e = tid; e < 2 * ncell; e += nt) {
-        const int half = e >= ncell ? 1 : 0, q = e - half * ncell;
-        const int i = q % NP, j = q / NP;
-        T y[5];
-        cc_half<T>(L, X, i, j, half, y);
-        for (int k2 = 0; k2 < 2; ++k2) {
-          const int cls = 2 * half + k2;
-          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
-          if (!interior(a, b)) continue;
-          for (int c = 0; c < 2; ++c) Tv.u(c, a, b) = F.u(c, a, b) - y[2 * k2 + c];
-        }
-        if (half) Tv.p(i, j) = F.p(i, j) - y[4];
-      }
-      __syncthreads();
-      const CVec<T> Fc = vec(l - 1, 1), Xc = vec(l - 1, 0);
-      const int Nc = Fc.N, NPc = Nc + 1;
-      for (int e = tid; e < NPc * NPc; e += nt) {
-        const int I = e % NPc, Jc = e / NPc;
-        for (int cls = 0; cls < 4; ++cls) {
-          const int A = 2 * I + (cls & 1), B = 2 * Jc + (cls >> 1);
-          if (!(A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)) continue;
-          for (int c = 0; c < 2; ++c) {
-            auto R = [&](int fa, int fb) -> T { return Tv.u(c, 2 * A + fa, 2 * B + fb); };
-            T v;
-            if (cls == 0) v = cell_res<0, T>(R);
-            else if (cls == 1) v = cell_res<1, T>(R);
-            else if (cls == 2) v = cell_res<2, T>(R);
-            else v = cell_res<3, T>(R);
-            Fc.u(c, A, B) = v;
-            Xc.u(c, A, B) = T(0);
-          }
-        }
-        auto Rp = [&](int di, int dj) -> T {
-          const int fi = 2 * I + di, fj = 2 * Jc + dj;
-          return (fi >= 0 && fi <= N && fj >= 0 && fj <= N) ? Tv.p(fi, fj) : T(0);
-        };
-        Fc.p(I, Jc) = Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1));
-        Xc.p(I, Jc) = T(0);
-      }
-      __syncthreads();
-    } else if (kind == CC_PROLONG) {
-      // X_l += P X_{l-1}: one thread per coarse square, 16 fine points each
-      const CVec<T> Xc = vec(l - 1, 0);
-      const int Nc = Xc.N, NPc = Nc + 1;
-      for (int e = tid; e < NPc * NPc; e += nt) {
-        const int I = e % NPc, Jc = e / NPc;
-        for (int c = 0; c < 2; ++c) {
-          auto Z = [&](int dA, int dB) -> T { return Xc.u(c, 2 * I + dA, 2 * Jc + dB); };
-          auto IN = [&](int ra, int rb) { return interior(4 * I + ra, 4 * Jc + rb); };
-          auto XR = [&](int ra, int rb) -> T& { return X.u(c, 4 * I + ra, 4 * Jc + rb); };
-          pro_block<T>(XR, IN, Z);
-        }
-      }
-      for (int e = tid; e < ncell; e += nt) {
-        const int i = e % NP, j = e / NP, I = i >> 1, Jc = j >> 1;
-        T z;
-        if (!(i & 1) && !(j & 1)) z = Xc.p(I, Jc);
-        else if ((i & 1) && !(j & 1)) z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I + 1, Jc));
-        else if (!(i & 1) && (j & 1)) z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I, Jc + 1));
-        else z = T(0.5) * (Xc.p(I, Jc) + Xc.p(I + 1, Jc + 1));
-        X.p(i, j) += z;
-      }
-      __syncthreads();
-    } else if (kind == CC_COARSE) {
-      // exact solve on level 0: z = Cinv [F; 0] in the compact order
-      const int M0 = 2 * N + 1, ni = 2 * N - 1, nu = ni * ni;
-      const int nc = J.nc;
-      T* r = Tv.v;  // reuse T of level 0 as the compact right-hand side
-      for (int k2 = tid; k2 < nc; k2 += nt) {
-        T v = T(0);
-        if (k2 < 2 * nu) {
-          const int c = k2 / nu, q = k2 % nu;
-          v = F.u(c, 1 + q % ni, 1 + q / ni);
-        } else if (k2 < 2 * nu + NP * NP) {
-          const int q = k2 - 2 * nu;
-          v = F.p(q % NP, q / NP);
-        }
-        r[k2] = v;
-      }
-      __syncthreads();
-      T zr[4];
-      int cnt = 0;
-      for (int row = tid; row < nc && cnt < 4; row += nt, ++cnt) {
-        double z = 0.0;
-        for (int q = 0; q < nc; ++q) z += J.cinv[(size_t)q * nc + row] * (double)r[q];
-        zr[cnt] = (T)z;
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int row = tid; row < nc && cnt < 4; row += nt, ++cnt) {
-        if (row < 2 * nu) {
-          const int c = row / nu, q = row % nu;
-          X.u(c, 1 + q % ni, 1 + q / ni) = zr[cnt];
-        } else if (row < 2 * nu + NP * NP) {
-          const int q = row - 2 * nu;
-          X.p(q % NP, q / NP) = zr[cnt];
-        }
-      }
-      __syncthreads();
-      (void)M0;
-    }
-  }
-  // store X of level Lc
-  {
-    const CVec<T> X = vec(Lc, 0);
-    const int N = X.N, M = 2 * N + 1, NP = N + 1;
-    for (int e = tid; e < 2 * M * M; e += nt) {
-      const int c = e / (M * M), q = e % (M * M), a = q % M, b = q / M;
-      J.xu[e] = (a > 0 && a < 2 * N && b > 0 && b < 2 * N) ? X.u(c, a, b) : T(0);
-    }
-    for (int e = tid; e < NP * NP; e += nt) J.xp[e] = X.p(e % NP, e / NP);
-  }
-}
+#include "smg_coarse.inc"
 
 template <class T>
 __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
@@ -786,9 +458,18 @@ __global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
 
 template <class T>
 __global__ __launch_bounds__(512) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
-  const CoarseJob<T>& J = jobs[blockIdx.x];
-  if (J.done && *J.done) return;
-  coarse_body<T>(J);
+  // the job (about 1.4 KB of coefficients and pointers) is staged in LDS once;
+  // read through global memory, every coefficient access inside the phases
+  // would be a vector load
+  __shared__ CoarseJob<T> sj;
+  {
+    const unsigned* src = reinterpret_cast<const unsigned*>(jobs + blockIdx.x);
+    unsigned* dst = reinterpret_cast<unsigned*>(&sj);
+    for (int e = threadIdx.x; e < (int)(sizeof(CoarseJob<T>) / 4); e += blockDim.x) dst[e] = src[e];
+  }
+  __syncthreads();
+  if (sj.done && *sj.done) return;
+  coarse_body<T>(sj);
 }
 
 template <class T>
