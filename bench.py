@@ -81,6 +81,22 @@ def cpu_baseline(n_cycles=30):
                       f"({len(BETAS) * n_cycles} cycles, {t_total:.1f} s, 1 thread, setup excluded)"}
 
 
+def copy_calibration(mib=512, reps=5):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: the reference
+    kernel against which the HBM byte counters are scaled (it reads and writes
+    exactly `mib` MiB per launch)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                                           "launches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -99,6 +117,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     F, G = inputs.uniform_f(N_GRID, seed=0)
     Fd = torch.from_numpy(F).cuda()
     Gd = torch.from_numpy(G).cuda()

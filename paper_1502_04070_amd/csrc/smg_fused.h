@@ -79,14 +79,12 @@ void launch_project_check(const double* mpart, const double* rpart, int np, int 
 // batched launches: many jobs (one per instance and level) in one grid.  A
 // block map entry holds (job << 20) | tile; jobs live in device memory.
 // ---------------------------------------------------------------------------
-constexpr int BMAP_SHIFT = 20;
-inline int bmap(int job, int tile) { return (job << BMAP_SHIFT) | tile; }
 
 template <class T>
-void launch_ne_b(const NEJob<T>* jobs, const int* map, int nb, int tx, bool zg, bool pro,
+void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro,
                  hipStream_t s);
 template <class T>
-void launch_rr_b(const RRJob<T>* jobs, const int* map, int nb, hipStream_t s);
+void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, hipStream_t s);
 template <class T>
 void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s);
 
@@ -100,6 +98,6 @@ struct PCJob {
   double* hist;
 };
 __host__ __device__ int pc_blocks(int N);
-void launch_pc_b(const PCJob* jobs, const int* map, int nb, hipStream_t s);
+void launch_pc_b(const JobArg<PCJob>& A, int nb, hipStream_t s);
 
 }  // namespace smg

@@ -96,6 +96,32 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   const int tid = threadIdx.x;
   auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
 
+  // Every global input the workgroup needs is requested before the first
+  // wait: the done flag, this thread's stage-1 right-hand side and Shat^-1
+  // (one stage-1 square per thread) and its stage-2 Shat^-1, then the
+  // iterate window.  The flag is tested once the window is in LDS.
+  static_assert((TX + 2) * (TY + 2) <= NT, "one stage-1 square per thread");
+  const int dn = J.done ? *J.done : 0;
+  const int c1i = tid % (TX + 2), c1j = tid / (TX + 2);
+  const int i1 = i0 - 1 + c1i, j1 = j0 - 1 + c1j;
+  const bool act1 = tid < (TX + 2) * (TY + 2);
+  T f1[9], s1 = T(0);
+#pragma unroll
+  for (int cls = 0; cls < 4; ++cls) {
+    const int a = 2 * i1 + (cls & 1), b = 2 * j1 + (cls >> 1);
+    const bool in = act1 && interior(a, b);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f1[2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+  }
+  const bool inp1 = act1 && i1 >= 0 && i1 <= N && j1 >= 0 && j1 <= N;
+  f1[8] = inp1 ? J.fp[(size_t)j1 * NP + i1] : T(0);
+  if (inp1) s1 = J.L.sinv[(size_t)j1 * NP + i1];
+  T s2 = T(0);
+  {
+    const int q = tid % (TX * TY), i = i0 + q % TX, j = j0 + q / TX;
+    if (tid >= TX * TY && i <= N && j <= N) s2 = J.L.sinv[(size_t)j * NP + i];
+  }
+
   // ---- stage 0: the iterate on the tile plus two squares of halo
   if constexpr (!ZG) {
     if constexpr (PRO) {
@@ -165,11 +191,12 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
     __syncthreads();
   }
 
+  if (dn) return;   // uniform across the workgroup
+
   // ---- stage 1: y = L^-1 (F - A x) on the tile plus one square of halo
   double nrm = 0.0;
-  for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
-    const int ci = e % (TX + 2), cj = e / (TX + 2);
-    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+  if (act1) {
+    const int ci = c1i, cj = c1j, i = i1, j = j1;
     T y[9];
     if constexpr (ZG) {
 #pragma unroll
@@ -186,16 +213,15 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         T r = T(0);
-        if (in) r = J.fu[(size_t)c * M * M + (size_t)b * M + a] - y[2 * cls + c];
+        if (in) r = f1[2 * cls + c] - y[2 * cls + c];
         if (owned && in) nrm += (double)r * (double)r;
         sy[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
       }
     }
-    const bool inp = i >= 0 && i <= N && j >= 0 && j <= N;
     T rp = T(0);
-    if (inp) rp = J.fp[(size_t)j * NP + i] - y[8];
-    if (owned && inp) nrm += (double)rp * (double)rp;
-    syp[cj * YPW + ci] = inp ? J.L.sinv[(size_t)j * NP + i] * rp : T(0);
+    if (inp1) rp = f1[8] - y[8];
+    if (owned && inp1) nrm += (double)rp * (double)rp;
+    syp[cj * YPW + ci] = inp1 ? s1 * rp : T(0);
   }
   __syncthreads();
 
@@ -254,7 +280,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         const size_t g = (size_t)j * NP + i;
         T xo = T(0);
         if constexpr (!ZG) xo = sxp[(ty + 2) * XPW + tx + 2];
-        J.op[g] = xo + tau * J.L.sinv[g] * zp;
+        J.op[g] = xo + tau * s2 * zp;
       }
     }
   }
@@ -266,34 +292,35 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 
 template <class T, int TX, int TY, bool ZG, bool PRO>
 __global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
-  if (J.done && *J.done) return;
   ne_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <class T, int TX, int TY, bool ZG, bool PRO>
-__global__ __launch_bounds__(2 * TX* TY) void k_ne_b(const NEJob<T>* __restrict__ jobs,
-                                                     const int* __restrict__ map) {
-  const int m = map[xcd_remap(blockIdx.x, gridDim.x)];
-  const NEJob<T> J = jobs[m >> BMAP_SHIFT];
-  if (J.done && *J.done) return;
-  ne_tile<T, TX, TY, ZG, PRO>(J, m & ((1 << BMAP_SHIFT) - 1));
+template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK>
+__global__ __launch_bounds__(2 * TX* TY) void k_ne_b(const JobArg<NEJob<T>> A) {
+  int tile;
+  const NEJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  ne_tile<T, TX, TY, ZG, PRO>(J, tile);
+}
+
+template <class T, int TX, int TY, bool PACK>
+static void launch_ne_b_shape(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
+  if (zg) k_ne_b<T, TX, TY, true, false, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
+  else if (pro) k_ne_b<T, TX, TY, false, true, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
+  else k_ne_b<T, TX, TY, false, false, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
 }
 
 template <class T>
-void launch_ne_b(const NEJob<T>* jobs, const int* map, int nb, int tx, bool zg, bool pro,
-                 hipStream_t s) {
+void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, hipStream_t s) {
   if (tx == 16) {
-    if (zg) k_ne_b<T, 16, 8, true, false><<<nb, 256, 0, s>>>(jobs, map);
-    else if (pro) k_ne_b<T, 16, 8, false, true><<<nb, 256, 0, s>>>(jobs, map);
-    else k_ne_b<T, 16, 8, false, false><<<nb, 256, 0, s>>>(jobs, map);
+    if (A.n > 0) launch_ne_b_shape<T, 16, 8, true>(A, nb, zg, pro, s);
+    else launch_ne_b_shape<T, 16, 8, false>(A, nb, zg, pro, s);
   } else {
-    if (zg) k_ne_b<T, 8, 8, true, false><<<nb, 128, 0, s>>>(jobs, map);
-    else if (pro) k_ne_b<T, 8, 8, false, true><<<nb, 128, 0, s>>>(jobs, map);
-    else k_ne_b<T, 8, 8, false, false><<<nb, 128, 0, s>>>(jobs, map);
+    if (A.n > 0) launch_ne_b_shape<T, 8, 8, true>(A, nb, zg, pro, s);
+    else launch_ne_b_shape<T, 8, 8, false>(A, nb, zg, pro, s);
   }
 }
-template void launch_ne_b<double>(const NEJob<double>*, const int*, int, int, bool, bool, hipStream_t);
-template void launch_ne_b<float>(const NEJob<float>*, const int*, int, int, bool, bool, hipStream_t);
+template void launch_ne_b<double>(const JobArg<NEJob<double>>&, int, int, bool, bool, hipStream_t);
+template void launch_ne_b<float>(const JobArg<NEJob<float>>&, int, int, bool, bool, hipStream_t);
 
 TileShape ne_tile_shape(int N) {
   if (N >= 128) return {16, 8};
@@ -349,6 +376,26 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   const int I0 = (tile % ntx) * TC, J0 = (tile / ntx) * TC;
   const int tid = threadIdx.x;
   auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+  // the done flag and this thread's stage-1 right-hand sides (at most two
+  // squares per thread) are requested together with the iterate window
+  static_assert(NC1 * NC1 <= 2 * NT, "at most two stage-1 squares per thread");
+  const int dn = J.done ? *J.done : 0;
+  T f1[2][9];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int e = tid + it * NT, ci = e % NC1, cj = e / NC1;
+    const int i = 2 * I0 - 2 + ci, j = 2 * J0 - 2 + cj;
+    const bool act = e < NC1 * NC1;
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+      const bool in = act && interior(a, b);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) f1[it][2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+    }
+    const bool inp = act && i >= 0 && i <= N && j >= 0 && j <= N;
+    f1[it][8] = inp ? J.fp[(size_t)j * NP + i] : T(0);
+  }
   for (int e = tid; e < XW * XW; e += NT) {
     const int la = e % XW, lb = e / XW;
     const int a = 4 * I0 - 6 + la, b = 4 * J0 - 6 + lb;
@@ -363,8 +410,12 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     sxp[e] = (i >= 0 && i <= N && j >= 0 && j <= N) ? J.xp[(size_t)j * NP + i] : T(0);
   }
   __syncthreads();
+  if (dn) return;   // uniform across the workgroup
   // stage 1: fine defect on squares [2 I0 - 2, 2 I0 + 2 TC] per side
-  for (int e = tid; e < NC1 * NC1; e += NT) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int e = tid + it * NT;
+    if (e >= NC1 * NC1) break;
     const int ci = e % NC1, cj = e / NC1;
     const int i = 2 * I0 - 2 + ci, j = 2 * J0 - 2 + cj;
     T y[9];
@@ -375,12 +426,10 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
       const int a = 2 * i + DA, b = 2 * j + DB;
       const bool in = interior(a, b);
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-        sr[c][2 * cj + DB][2 * ci + DA] =
-            in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] - y[2 * cls + c] : T(0);
+      for (int c = 0; c < 2; ++c) sr[c][2 * cj + DB][2 * ci + DA] = in ? f1[it][2 * cls + c] - y[2 * cls + c] : T(0);
     }
     const bool inp = i >= 0 && i <= N && j >= 0 && j <= N;
-    srp[cj * RPW + ci] = inp ? J.fp[(size_t)j * NP + i] - y[8] : T(0);
+    srp[cj * RPW + ci] = inp ? f1[it][8] - y[8] : T(0);
   }
   __syncthreads();
   // stage 2: one wave per coarse node class, one lane per coarse square
@@ -418,25 +467,23 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
 
 template <class T>
 __global__ __launch_bounds__(256) void k_resid_restrict(RRJob<T> J) {
-  if (J.done && *J.done) return;
   rr_tile<T>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_rr_b(const RRJob<T>* __restrict__ jobs,
-                                              const int* __restrict__ map) {
-  const int m = map[xcd_remap(blockIdx.x, gridDim.x)];
-  const RRJob<T> J = jobs[m >> BMAP_SHIFT];
-  if (J.done && *J.done) return;
-  rr_tile<T>(J, m & ((1 << BMAP_SHIFT) - 1));
+template <class T, bool PACK>
+__global__ __launch_bounds__(256) void k_rr_b(const JobArg<RRJob<T>> A) {
+  int tile;
+  const RRJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  rr_tile<T>(J, tile);
 }
 
 template <class T>
-void launch_rr_b(const RRJob<T>* jobs, const int* map, int nb, hipStream_t s) {
-  k_rr_b<T><<<nb, 256, 0, s>>>(jobs, map);
+void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_rr_b<T, true><<<nb, 256, 0, s>>>(A);
+  else k_rr_b<T, false><<<nb, 256, 0, s>>>(A);
 }
-template void launch_rr_b<double>(const RRJob<double>*, const int*, int, hipStream_t);
-template void launch_rr_b<float>(const RRJob<float>*, const int*, int, hipStream_t);
+template void launch_rr_b<double>(const JobArg<RRJob<double>>&, int, hipStream_t);
+template void launch_rr_b<float>(const JobArg<RRJob<float>>&, int, hipStream_t);
 
 template <class T>
 void launch_resid_restrict(const RRJob<T>& J, hipStream_t s) {
@@ -450,14 +497,19 @@ template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
 // ---------------------------------------------------------------------------
 #include "smg_coarse.inc"
 
+// 12 waves: the nine item types of a phase on the levels up to N = 8 fit in
+// one pass, and the register budget (three waves per SIMD) still holds the
+// FP64 stencil rows without spills
+constexpr int CC_THREADS = 768;
+
 template <class T>
-__global__ __launch_bounds__(512) void k_coarse_cycle(CoarseJob<T> J) {
+__global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle(CoarseJob<T> J) {
   if (J.done && *J.done) return;
   coarse_body<T>(J);
 }
 
 template <class T>
-__global__ __launch_bounds__(512) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
+__global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
   // the job (about 1.4 KB of coefficients and pointers) is staged in LDS once;
   // read through global memory, every coefficient access inside the phases
   // would be a vector load
@@ -474,7 +526,7 @@ __global__ __launch_bounds__(512) void k_coarse_cycle_b(const CoarseJob<T>* __re
 
 template <class T>
 void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s) {
-  k_coarse_cycle_b<T><<<njobs, 512, lds, s>>>(jobs);
+  k_coarse_cycle_b<T><<<njobs, CC_THREADS, lds, s>>>(jobs);
 }
 template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, hipStream_t);
 template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, hipStream_t);
@@ -491,7 +543,7 @@ size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
 template <class T>
 int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s) {
   const size_t lds = coarse_cycle_lds(J.n0, J.Lc, sizeof(T));
-  k_coarse_cycle<T><<<1, 512, lds, s>>>(J);
+  k_coarse_cycle<T><<<1, CC_THREADS, lds, s>>>(J);
   return 0;
 }
 template int launch_coarse_cycle<double>(const CoarseJob<double>&, hipStream_t);
@@ -609,16 +661,17 @@ void launch_project_check(const double* mpart, const double* rpart, int np, int 
   k_project_check<<<pc_blocks(N), 256, 0, s>>>(mpart, rpart, np, N, p, st, hist);
 }
 
-__global__ __launch_bounds__(256) void k_pc_b(const PCJob* __restrict__ jobs, const int* __restrict__ map) {
-  const int m = map[blockIdx.x];
-  const PCJob J = jobs[m >> BMAP_SHIFT];
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_pc_b(const JobArg<PCJob> A) {
+  int tile;
+  const PCJob J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.st->done) return;
-  project_check_body(J.mpart, J.rpart, J.np, J.N, J.p, J.st, J.hist, m & ((1 << BMAP_SHIFT) - 1),
-                     pc_blocks(J.N));
+  project_check_body(J.mpart, J.rpart, J.np, J.N, J.p, J.st, J.hist, tile, pc_blocks(J.N));
 }
 
-void launch_pc_b(const PCJob* jobs, const int* map, int nb, hipStream_t s) {
-  k_pc_b<<<nb, 256, 0, s>>>(jobs, map);
+void launch_pc_b(const JobArg<PCJob>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_pc_b<true><<<nb, 256, 0, s>>>(A);
+  else k_pc_b<false><<<nb, 256, 0, s>>>(A);
 }
 
 }  // namespace smg

@@ -6,6 +6,42 @@
 
 namespace smg {
 
+// The jobs of one batched launch.  Up to PACK_MAX jobs travel by value in the
+// kernel arguments, with the first workgroup of each job, so a workgroup finds
+// its job without a round trip to memory.  Larger batches use a device job
+// table and a block map ((job << BMAP_SHIFT) | tile per workgroup); then n = 0.
+constexpr int PACK_MAX = 8;
+constexpr int BMAP_SHIFT = 20;
+inline int bmap(int job, int tile) { return (job << BMAP_SHIFT) | tile; }
+
+template <class J>
+struct JobArg {
+  const J* jobs;
+  const int* map;
+  int n;
+  int start[PACK_MAX + 1];
+  J pack[PACK_MAX];
+};
+
+// The job of workgroup b (after any block remapping) and its tile index, from
+// the packed jobs (PACK) or from the table.  The two sources are separate
+// instantiations, so that each reads its job through one address space with
+// scalar loads.
+template <bool PACK, class J>
+__device__ __forceinline__ J block_job(const JobArg<J>& A, int b, int& tile) {
+  if constexpr (PACK) {
+    int k = 0;
+#pragma unroll
+    for (int q = 1; q < PACK_MAX; ++q) k += (q < A.n && b >= A.start[q]) ? 1 : 0;
+    tile = b - A.start[k];
+    return A.pack[k];
+  } else {
+    const int m = A.map[b];
+    tile = m & ((1 << BMAP_SHIFT) - 1);
+    return A.jobs[m >> BMAP_SHIFT];
+  }
+}
+
 // Per-level constants of the operator (Section 2 matrices, Section 6
 // preconditioner), in the arithmetic type T of the kernels.
 template <class T>
@@ -57,7 +93,7 @@ template <class T>
 unsigned stencil_flags(const StencilJob<T>& J, int rows);
 // batched: jobs with identical flags, one tile shape (tx, ty) for all
 template <class T>
-void launch_stencil_b(const StencilJob<T>* jobs, const int* map, int nb, int tx, int ty,
+void launch_stencil_b(const JobArg<StencilJob<T>>& A, int nb, int tx, int ty,
                       unsigned flags, hipStream_t s);
 int stencil_tiles_shape(int N, int tx, int ty);
 
@@ -73,7 +109,7 @@ struct ProJob {
 };
 int prolong_tiles(int Nc);
 template <class T>
-void launch_prolong_b(const ProJob<T>* jobs, const int* map, int nb, hipStream_t s);
+void launch_prolong_b(const JobArg<ProJob<T>>& A, int nb, hipStream_t s);
 
 // batched elementwise: cast d -> f (mode 0), d += f (mode 1), d = 0 (mode 2)
 struct EwJob {
@@ -83,7 +119,7 @@ struct EwJob {
   const int* done;
 };
 int ew_tiles(int64_t n);
-void launch_ew_b(const EwJob* jobs, const int* map, int nb, int mode, hipStream_t s);
+void launch_ew_b(const JobArg<EwJob>& A, int nb, int mode, hipStream_t s);
 
 // r_c = P^T r_f (velocity P2, pressure P1); also zero (xcu, xcp) if not NULL.
 template <class T>

@@ -334,42 +334,45 @@ template unsigned stencil_flags<float>(const StencilJob<float>&, int);
 
 int stencil_tiles_shape(int N, int tx, int ty) { return ((N + tx) / tx) * ((N + ty) / ty); }
 
-template <class T, int TX, int TY, unsigned F>
-__global__ __launch_bounds__(TX* TY) void k_stencil_b(const StencilJob<T>* __restrict__ jobs,
-                                                     const int* __restrict__ map) {
-  const int m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
-  const StencilJob<T> J = jobs[m >> 20];
+template <class T, int TX, int TY, unsigned F, bool PACK>
+__global__ __launch_bounds__(TX* TY) void k_stencil_b(const JobArg<StencilJob<T>> A) {
+  int tile;
+  const StencilJob<T> J = block_job<PACK>(A, xcd_swizzle(blockIdx.x, gridDim.x), tile);
   if (J.done && *J.done) return;
-  stencil_tile<T, TX, TY, F>(J, m & ((1 << 20) - 1));
+  stencil_tile<T, TX, TY, F>(J, tile);
 }
 
 template <class T, int TX, int TY>
-static void launch_stencil_b_shape(const StencilJob<T>* jobs, const int* map, int nb, unsigned f,
-                                   hipStream_t s) {
-#define SMG_CASE(MODE) \
-  case MODE: k_stencil_b<T, TX, TY, MODE><<<nb, TX * TY, 0, s>>>(jobs, map); return;
+static void launch_stencil_b_shape(const JobArg<StencilJob<T>>& A, int nb, unsigned f, hipStream_t s) {
+#define SMG_CASE(MODE)                                                          \
+  case MODE:                                                                    \
+    if (A.n > 0) k_stencil_b<T, TX, TY, MODE, true><<<nb, TX * TY, 0, s>>>(A);  \
+    else k_stencil_b<T, TX, TY, MODE, false><<<nb, TX * TY, 0, s>>>(A);         \
+    return;
   switch (f) {
     SMG_CASE(M_APPLY) SMG_CASE(M_RESID) SMG_CASE(M_RESID_NORM) SMG_CASE(M_RESID_BOTH)
     SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
     SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
     SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
     SMG_CASE(M_MASK_U) SMG_CASE(M_COPY) SMG_CASE(M_ZERO)
-    default: k_stencil_b<T, TX, TY, 0u><<<nb, TX * TY, 0, s>>>(jobs, map); return;
+    default:
+      if (A.n > 0) k_stencil_b<T, TX, TY, 0u, true><<<nb, TX * TY, 0, s>>>(A);
+      else k_stencil_b<T, TX, TY, 0u, false><<<nb, TX * TY, 0, s>>>(A);
+      return;
   }
 #undef SMG_CASE
 }
 
 template <class T>
-void launch_stencil_b(const StencilJob<T>* jobs, const int* map, int nb, int tx, int ty,
-                      unsigned flags, hipStream_t s) {
-  if (tx == 16 && ty == 16) launch_stencil_b_shape<T, 16, 16>(jobs, map, nb, flags, s);
-  else if (tx == 16 && ty == 8) launch_stencil_b_shape<T, 16, 8>(jobs, map, nb, flags, s);
-  else launch_stencil_b_shape<T, 8, 8>(jobs, map, nb, flags, s);
+void launch_stencil_b(const JobArg<StencilJob<T>>& A, int nb, int tx, int ty, unsigned flags,
+                      hipStream_t s) {
+  if (tx == 16 && ty == 16) launch_stencil_b_shape<T, 16, 16>(A, nb, flags, s);
+  else if (tx == 16 && ty == 8) launch_stencil_b_shape<T, 16, 8>(A, nb, flags, s);
+  else launch_stencil_b_shape<T, 8, 8>(A, nb, flags, s);
 }
-template void launch_stencil_b<double>(const StencilJob<double>*, const int*, int, int, int, unsigned,
+template void launch_stencil_b<double>(const JobArg<StencilJob<double>>&, int, int, int, unsigned,
                                        hipStream_t);
-template void launch_stencil_b<float>(const StencilJob<float>*, const int*, int, int, int, unsigned,
-                                      hipStream_t);
+template void launch_stencil_b<float>(const JobArg<StencilJob<float>>&, int, int, int, unsigned, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // transfers (Section 3): one thread per coarse square
@@ -501,22 +504,22 @@ __global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict
 
 int prolong_tiles(int Nc) { return ((Nc + 16) / 16) * ((Nc + 16) / 16); }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_prolong_b(const ProJob<T>* __restrict__ jobs,
-                                                   const int* __restrict__ map) {
-  const int m = map[blockIdx.x];
-  const ProJob<T> J = jobs[m >> 20];
+template <class T, bool PACK>
+__global__ __launch_bounds__(256) void k_prolong_b(const JobArg<ProJob<T>> A) {
+  int tile;
+  const ProJob<T> J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.done && *J.done) return;
-  const int tile = m & ((1 << 20) - 1), ntx = (J.Nc + 16) / 16;
+  const int ntx = (J.Nc + 16) / 16;
   prolong_body<T>(J.Nc, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
 }
 
 template <class T>
-void launch_prolong_b(const ProJob<T>* jobs, const int* map, int nb, hipStream_t s) {
-  k_prolong_b<T><<<nb, 256, 0, s>>>(jobs, map);
+void launch_prolong_b(const JobArg<ProJob<T>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_prolong_b<T, true><<<nb, 256, 0, s>>>(A);
+  else k_prolong_b<T, false><<<nb, 256, 0, s>>>(A);
 }
-template void launch_prolong_b<double>(const ProJob<double>*, const int*, int, hipStream_t);
-template void launch_prolong_b<float>(const ProJob<float>*, const int*, int, hipStream_t);
+template void launch_prolong_b<double>(const JobArg<ProJob<double>>&, int, hipStream_t);
+template void launch_prolong_b<float>(const JobArg<ProJob<float>>&, int, hipStream_t);
 
 template <class T>
 void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
@@ -896,12 +899,12 @@ void launch_axpy_f32(double* x, const float* d, int64_t n, const int* done, hipS
 
 int ew_tiles(int64_t n) { return (int)((n + 1023) / 1024); }
 
-__global__ __launch_bounds__(256) void k_ew_b(const EwJob* __restrict__ jobs, const int* __restrict__ map,
-                                              int mode) {
-  const int m = map[blockIdx.x];
-  const EwJob J = jobs[m >> 20];
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_ew_b(const JobArg<EwJob> A, int mode) {
+  int tile;
+  const EwJob J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.done && *J.done) return;
-  const int64_t base = (int64_t)(m & ((1 << 20) - 1)) * 1024;
+  const int64_t base = (int64_t)tile * 1024;
   for (int k = 0; k < 4; ++k) {
     const int64_t e = base + k * 256 + threadIdx.x;
     if (e >= J.n) break;
@@ -911,8 +914,9 @@ __global__ __launch_bounds__(256) void k_ew_b(const EwJob* __restrict__ jobs, co
   }
 }
 
-void launch_ew_b(const EwJob* jobs, const int* map, int nb, int mode, hipStream_t s) {
-  k_ew_b<<<nb, 256, 0, s>>>(jobs, map, mode);
+void launch_ew_b(const JobArg<EwJob>& A, int nb, int mode, hipStream_t s) {
+  if (A.n > 0) k_ew_b<true><<<nb, 256, 0, s>>>(A, mode);
+  else k_ew_b<false><<<nb, 256, 0, s>>>(A, mode);
 }
 
 }  // namespace smg
