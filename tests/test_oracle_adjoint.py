@@ -70,3 +70,26 @@ def test_gradient_of_g_is_blind_to_constants():
     dLdu = lv.disc.mass_u() @ (x[: lv.nu2] - ut)
     _, dg, _ = adjoint.gradients(lv, x, dLdu, np.zeros(lv.n1))
     assert abs(dg.sum()) < 1e-12 * np.abs(dg).sum()
+
+
+def test_multigrid_solves_give_the_direct_gradients():
+    """The multigrid variant (used where a direct factorization is too large)
+    reproduces the direct-solve gradients to the solve tolerance."""
+    h = Hierarchy("same_diag", 3, 40.0, n0=2)
+    lv = h.top
+    rng = np.random.default_rng(5)
+    d = lv.disc
+    f = rng.standard_normal((2, d.n2))
+    g = rng.standard_normal(d.n1)
+    ut = rng.standard_normal(lv.nu2)
+    wp = rng.standard_normal(lv.n1)
+    out = []
+    for solve in (None, adjoint.mg_solver(h, tol=1e-13)):
+        x = adjoint.forward(lv, f, g, solve=solve)
+        dLdu = d.mass_u() @ (x[: lv.nu2] - ut)
+        out.append((x,) + adjoint.gradients(lv, x, dLdu, wp, solve=solve))
+    (x0, df0, dg0, db0), (x1, df1, dg1, db1) = out
+    assert np.linalg.norm(x1 - x0) <= 1e-11 * np.linalg.norm(x0)
+    assert np.abs(df1 - df0).max() <= 1e-9 * np.abs(df0).max()
+    assert np.abs(dg1 - dg0).max() <= 1e-9 * np.abs(dg0).max()
+    assert abs(db1 - db0) <= 1e-9 * abs(db0)
