@@ -108,6 +108,7 @@ struct smg_hier {
   int cc_nops = 0;
   double* mpart = nullptr;         // pressure-mean partials of the finest level
   bool fused = true;
+  bool ne2 = true;                 // pairs of normal-equation steps in one launch (8 x 8 levels)
   std::vector<void*> allocs;
 
   template <class T>
@@ -437,7 +438,9 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     fill_vec<T>(L, cur, s);
     z = false;
   }
-  for (int k = 0; k < prm.nu_pre; ++k) {
+  // two steps per launch where the level uses 8 x 8 tiles
+  const bool pair = ne && H->ne2 && ne_tile_shape(L.N).tx == 8;
+  for (int k = 0; k < prm.nu_pre;) {
     if (ne) {
       NEJob<T> J{};
       J.L = Sel<T>::c(L);
@@ -446,12 +449,16 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.ou = alt.u; J.op = alt.p;
       J.tau = T(prm.tau);
       J.done = done;
-      launch_ne<T>(J, z, false, s);
+      const bool two = pair && k + 1 < prm.nu_pre;
+      if (two) launch_ne2<T>(J, z, false, s);
+      else launch_ne<T>(J, z, false, s);
       std::swap(cur, alt);
+      k += two ? 2 : 1;
     } else {
       // Uzawa: three passes through the level's t buffer, result in place
       // (t is free here: the iterate stays in cur)
       smooth_step<T>(prm, L, cur, f, alt, z, done, s);
+      ++k;
     }
     z = false;
   }
@@ -480,13 +487,15 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     J.zu = zc.u; J.zp = zc.p;
     J.tau = T(prm.tau);
     J.done = done;
-    launch_ne<T>(J, false, true, s);
+    const bool two = pair && post >= 2;
+    if (two) launch_ne2<T>(J, false, true, s);
+    else launch_ne<T>(J, false, true, s);
     std::swap(cur, alt);
-    --post;
+    post -= two ? 2 : 1;
   } else {
     launch_prolong_add<T>(C.N, zc.u, zc.p, cur.u, cur.p, done, s);
   }
-  for (int k = 0; k < post; ++k) {
+  for (int k = 0; k < post;) {
     if (ne) {
       NEJob<T> J{};
       J.L = Sel<T>::c(L);
@@ -495,10 +504,14 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.ou = alt.u; J.op = alt.p;
       J.tau = T(prm.tau);
       J.done = done;
-      launch_ne<T>(J, false, false, s);
+      const bool two = pair && k + 1 < post;
+      if (two) launch_ne2<T>(J, false, false, s);
+      else launch_ne<T>(J, false, false, s);
       std::swap(cur, alt);
+      k += two ? 2 : 1;
     } else {
       smooth_step<T>(prm, L, cur, f, alt, false, done, s);
+      ++k;
     }
   }
   return cur;
@@ -717,6 +730,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   H->prm = prm;
   H->beta = beta;
   H->fused = prm.unfused == 0;
+  // tuning knob SMG_NE2=0: one launch per normal-equation step everywhere
+  if (const char* ev = std::getenv("SMG_NE2")) H->ne2 = std::atoi(ev) != 0;
   H->L = L;
   if (hipGetDevice(&H->device) != hipSuccess) { delete H; return fail(SMG_EHIP, "hipGetDevice"); }
   H->lv.resize(L + 1);
@@ -789,7 +804,7 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     delete H;
     return fail(SMG_EHIP, "setup upload / kernels failed");
   }
-  // levels handled by the single-workgroup kernel: N <= 16 and all three
+  // levels handled by the single-workgroup kernel: N <= cmax and all three
   // vectors of every such level in FP64 within the LDS of one workgroup
   {
     int lds_max = 0, lds_optin = 0;
@@ -798,8 +813,10 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     const size_t limit = (size_t)std::max(lds_max, lds_optin);
     H->Lc = -1;
     // largest grid done by the single-workgroup kernel (tuning knob
-    // SMG_COARSE_MAX_N, default 16 squares per side)
-    int cmax = 16;
+    // SMG_COARSE_MAX_N, default 8 squares per side: from N = 16 on, the grid
+    // kernels with two smoothing steps per launch finish a level sooner than
+    // one workgroup does)
+    int cmax = 8;
     if (const char* ev = std::getenv("SMG_COARSE_MAX_N")) cmax = std::max(0, std::atoi(ev));
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
       if ((prm.n0 << l) > cmax) break;

@@ -21,6 +21,12 @@ struct NEJob {
   const int* done;
 };
 TileShape ne_tile_shape(int N);
+// two normal-equation steps in one launch (8 x 8 tiles; levels with N < 128):
+// the output is the iterate after both steps; the partial field is not used
+template <class T>
+void launch_ne2(const NEJob<T>& J, bool zero_guess, bool prolong, hipStream_t s);
+template <class T>
+void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zero_guess, bool prolong, hipStream_t s);
 int ne_tiles(int N);
 template <class T>
 void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, hipStream_t s);

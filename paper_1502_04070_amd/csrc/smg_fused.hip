@@ -6,17 +6,20 @@
 //                   Optionally the coarse-grid correction x += P z (Section 3)
 //                   is applied to x while it is staged (the first
 //                   post-smoothing step absorbs the prolongation).
+//   k_ne2           two normal-equation steps in one launch on levels with
+//                   8 x 8 tiles: every intermediate lives in LDS on the tile
+//                   plus a halo that shrinks by one square per operator.
 //   k_resid_restrict  the defect F - A x and its restriction P^T (F - A x)
 //                   (Section 3) in one launch; the fine defect lives only in LDS.
-//   k_coarse_cycle  the whole iterate on the coarse levels (N <= 16) by one
-//                   workgroup with every vector of those levels in LDS,
+//   k_coarse_cycle  the whole iterate on the coarse levels (N <= 8 by default)
+//                   by one workgroup with every vector of those levels in LDS,
 //                   including the exact solve on level 0.
 //   k_project_partials  the pressure mean projection from partial sums that
 //                   the residual-norm pass of the solve loop produces.
 //
 // Bandwidth: an unfused normal-equation step streams x, F and the
 // intermediate twice (6 vectors); k_ne streams x and F once and writes x once
-// (3 vectors).  k_resid_restrict reads x and F and writes a quarter-size
+// (3 vectors); k_ne2 does two steps for the same three vectors.  k_resid_restrict reads x and F and writes a quarter-size
 // coarse vector instead of writing and re-reading the fine defect.
 #include "smg_cell.h"
 #include "smg_fused.h"
@@ -353,6 +356,276 @@ void launch_ne(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
 }
 template void launch_ne<double>(const NEJob<double>&, bool, bool, hipStream_t);
 template void launch_ne<float>(const NEJob<float>&, bool, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// k_ne2: two fused normal-equation steps on a TX x TY tile of squares
+// ---------------------------------------------------------------------------
+// Applying calA on a set of squares needs its argument on the points owned by
+// that set plus one square around it.  The second step's result on the tile
+// therefore needs the first step's result on the tile plus two squares (X1),
+// the first scaled residual on the tile plus three (Y1) and the iterate on the
+// tile plus four (X0); F and Shat^-1 are staged on the tile plus three.  The
+// second residual (Y2, tile plus one) reuses Y1's storage.  Every window is a
+// lattice of the points owned by its squares, zero outside the interior of the
+// velocity space and outside the grid.  Each value is computed by the same
+// expressions as in two single steps.
+
+template <class T, int TX, int TY, bool ZG, bool PRO>
+__device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
+  constexpr int NT = 4 * TX * TY;
+  constexpr int W4 = 2 * TX + 16, H4 = 2 * TY + 16, PW4 = TX + 8, PH4 = TY + 8;   // X0: tile + 4
+  constexpr int W3 = 2 * TX + 12, H3 = 2 * TY + 12, PW3 = TX + 6, PH3 = TY + 6;   // F, Y1, Shat^-1: + 3
+  constexpr int W2 = 2 * TX + 8, H2 = 2 * TY + 8, PW2 = TX + 4, PH2 = TY + 4;     // X1: + 2
+  constexpr int W1 = 2 * TX + 4, H1 = 2 * TY + 4, PW1 = TX + 2;                   // Y2: + 1
+  static_assert((TX + 6) * (TY + 6) <= NT, "one stage-1 square per thread");
+  __shared__ T sx0[ZG ? 1 : 2][ZG ? 1 : H4][ZG ? 1 : W4];
+  __shared__ T sx0p[ZG ? 1 : PH4 * PW4];
+  __shared__ T sf[2][H3][W3];
+  __shared__ T sfp[PH3 * PW3];
+  __shared__ T ss[PH3 * PW3];
+  __shared__ T sy[2][H3][W3];
+  __shared__ T syp[PH3 * PW3];
+  __shared__ T sx1[2][H2][W2];
+  __shared__ T sx1p[PH2 * PW2];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int ntx = (N + TX) / TX;
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  const T tau = J.tau;
+  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+  auto inside = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
+
+  // ---- stage 0: F and Shat^-1 on the tile + 3, the iterate on the tile + 4
+  const int dn = J.done ? *J.done : 0;
+  for (int e = tid; e < W3 * H3; e += NT) {
+    const int la = e % W3, lb = e / W3;
+    const int a = 2 * i0 - 6 + la, b = 2 * j0 - 6 + lb;
+    const bool in = interior(a, b);
+    const size_t g = (size_t)b * M + a;
+    sf[0][lb][la] = in ? J.fu[g] : T(0);
+    sf[1][lb][la] = in ? J.fu[(size_t)M * M + g] : T(0);
+  }
+  for (int e = tid; e < PW3 * PH3; e += NT) {
+    const int i = i0 - 3 + e % PW3, j = j0 - 3 + e / PW3;
+    const bool ok = inside(i, j);
+    sfp[e] = ok ? J.fp[(size_t)j * NP + i] : T(0);
+    ss[e] = ok ? J.L.sinv[(size_t)j * NP + i] : T(0);
+  }
+  if constexpr (!ZG) {
+    if constexpr (PRO) {
+      // x + P z_c: one item per (coarse square of the window, component, fine row)
+      constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4;
+      const int Nc = N / 2, Mc = 2 * Nc + 1;
+      for (int e = tid; e < CW * CH * 8; e += NT) {
+        const int rb = e / (2 * CW * CH), rem = e % (2 * CW * CH);
+        const int c = rem / (CW * CH), cell = rem % (CW * CH);
+        const int ci = cell % CW, cj = cell / CW;
+        const int I = i0 / 2 - 2 + ci, Jc = j0 / 2 - 2 + cj;
+        T z[3][3];
+#pragma unroll
+        for (int dB = 0; dB < 3; ++dB)
+#pragma unroll
+          for (int dA = 0; dA < 3; ++dA) {
+            const int A = 2 * I + dA, B = 2 * Jc + dB;
+            z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
+                            ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
+          }
+        auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
+        const int b = 4 * Jc + rb;
+        T v[4];
+#pragma unroll
+        for (int ra = 0; ra < 4; ++ra) {
+          const int a = 4 * I + ra;
+          v[ra] = interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+        }
+        switch (rb) {
+#define SMG_ROW(RB)                                                              \
+  case RB:                                                                       \
+    if (interior(4 * I + 0, b)) v[0] += pro_w<0, RB, T>(Z);                      \
+    if (interior(4 * I + 1, b)) v[1] += pro_w<1, RB, T>(Z);                      \
+    if (interior(4 * I + 2, b)) v[2] += pro_w<2, RB, T>(Z);                      \
+    if (interior(4 * I + 3, b)) v[3] += pro_w<3, RB, T>(Z);                      \
+    break;
+          SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
+#undef SMG_ROW
+        }
+#pragma unroll
+        for (int ra = 0; ra < 4; ++ra) sx0[c][4 * cj + rb][4 * ci + ra] = v[ra];
+      }
+      for (int e = tid; e < PW4 * PH4; e += NT) {
+        const int i = i0 - 4 + e % PW4, j = j0 - 4 + e / PW4;
+        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j) : T(0);
+      }
+    } else {
+      for (int e = tid; e < W4 * H4; e += NT) {
+        const int la = e % W4, lb = e / W4;
+        const int a = 2 * i0 - 8 + la, b = 2 * j0 - 8 + lb;
+        const bool in = interior(a, b);
+        const size_t g = (size_t)b * M + a;
+        sx0[0][lb][la] = in ? J.xu[g] : T(0);
+        sx0[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
+      }
+      for (int e = tid; e < PW4 * PH4; e += NT) {
+        const int i = i0 - 4 + e % PW4, j = j0 - 4 + e / PW4;
+        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+      }
+    }
+  }
+  __syncthreads();
+  if (dn) return;   // uniform across the workgroup
+
+  // ---- stage 1: Y1 = L^-1 (F - A X0) on the tile + 3
+  for (int e = tid; e < (TX + 6) * (TY + 6); e += NT) {
+    const int ci = e % (TX + 6), cj = e / (TX + 6);
+    const int i = i0 - 3 + ci, j = j0 - 3 + cj;
+    T y[9];
+    if constexpr (ZG) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) y[k] = T(0);
+    } else {
+      cell_apply<T, true, true, H4, W4, PW4>(J.L, sx0, 2 * ci + 2, 2 * cj + 2, sx0p, ci + 1, cj + 1, y);
+    }
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const T r = sf[c][2 * cj + DB][2 * ci + DA] - y[2 * cls + c];
+        sy[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+      }
+    }
+    const int q = cj * PW3 + ci;
+    syp[q] = inside(i, j) ? ss[q] * (sfp[q] - y[8]) : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 2: X1 = X0 + tau L^-1 A Y1 on the tile + 2
+  for (int e = tid; e < (TX + 4) * (TY + 4); e += NT) {
+    const int ci = e % (TX + 4), cj = e / (TX + 4);
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    T z[9];
+    cell_apply<T, true, true, H3, W3, PW3>(J.L, sy, 2 * ci + 2, 2 * cj + 2, syp, ci + 1, cj + 1, z);
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+      const T d = J.L.adinv[cls] * tau;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T x0 = T(0);
+        if constexpr (!ZG) x0 = sx0[c][2 * cj + 4 + DB][2 * ci + 4 + DA];
+        sx1[c][2 * cj + DB][2 * ci + DA] = in ? x0 + d * z[2 * cls + c] : T(0);
+      }
+    }
+    T x0p = T(0);
+    if constexpr (!ZG) x0p = sx0p[(cj + 2) * PW4 + ci + 2];
+    sx1p[cj * PW2 + ci] = inside(i, j) ? x0p + tau * ss[(cj + 1) * PW3 + ci + 1] * z[8] : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 3: Y2 = L^-1 (F - A X1) on the tile + 1, in Y1's storage
+  T (*sy2)[H1][W1] = reinterpret_cast<T (*)[H1][W1]>(&sy[0][0][0]);
+  for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
+    const int ci = e % (TX + 2), cj = e / (TX + 2);
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    T y[9];
+    cell_apply<T, true, true, H2, W2, PW2>(J.L, sx1, 2 * ci + 2, 2 * cj + 2, sx1p, ci + 1, cj + 1, y);
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const T r = sf[c][2 * cj + 4 + DB][2 * ci + 4 + DA] - y[2 * cls + c];
+        sy2[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+      }
+    }
+    const int q3 = (cj + 2) * PW3 + ci + 2;
+    syp[cj * PW1 + ci] = inside(i, j) ? ss[q3] * (sfp[q3] - y[8]) : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 4: X2 = X1 + tau L^-1 A Y2 on the tile; four threads per square
+  {
+    const int part = tid / (TX * TY), q = tid % (TX * TY);
+    const int tx = q % TX, ty = q / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i <= N && j <= N) {
+      auto UA = [&](int c, int da, int db) -> T { return sy2[c][2 * ty + 2 + db][2 * tx + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return syp[(ty + 1 + dj) * PW1 + (tx + 1 + di)]; };
+      auto emit = [&](int cls, T z0, T z1) {
+        const int DA = cls & 1, DB = cls >> 1;
+        const int a = 2 * i + DA, b = 2 * j + DB;
+        if (a > 2 * N || b > 2 * N) return;
+        const bool in = interior(a, b);
+        const size_t g = (size_t)b * M + a;
+        const T d = J.L.adinv[cls] * tau;
+        J.ou[g] = in ? sx1[0][2 * ty + 4 + DB][2 * tx + 4 + DA] + d * z0 : T(0);
+        J.ou[(size_t)M * M + g] = in ? sx1[1][2 * ty + 4 + DB][2 * tx + 4 + DA] + d * z1 : T(0);
+      };
+      T z0, z1;
+      if (part == 0) {
+        auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, db); };
+        cell_vel<0, T, true, true>(J.L, Uc, PA, z0, z1);
+        emit(0, z0, z1);
+      } else if (part == 1) {
+        auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, db); };
+        cell_vel<1, T, true, true>(J.L, Uc, PA, z0, z1);
+        emit(1, z0, z1);
+      } else if (part == 2) {
+        auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, 1 + db); };
+        cell_vel<2, T, true, true>(J.L, Uc, PA, z0, z1);
+        emit(2, z0, z1);
+      } else {
+        auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, 1 + db); };
+        cell_vel<3, T, true, true>(J.L, Uc, PA, z0, z1);
+        emit(3, z0, z1);
+        auto U0 = [&](int da, int db) -> T { return UA(0, da, db); };
+        auto U1 = [&](int da, int db) -> T { return UA(1, da, db); };
+        const T zp = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+        J.op[(size_t)j * NP + i] = sx1p[(ty + 2) * PW2 + tx + 2] + tau * ss[(ty + 3) * PW3 + tx + 3] * zp;
+      }
+    }
+  }
+}
+
+template <class T, int TX, int TY, bool ZG, bool PRO>
+__global__ __launch_bounds__(4 * TX* TY) void k_ne2(NEJob<T> J) {
+  ne2_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK>
+__global__ __launch_bounds__(4 * TX* TY) void k_ne2_b(const JobArg<NEJob<T>> A) {
+  int tile;
+  const NEJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  ne2_tile<T, TX, TY, ZG, PRO>(J, tile);
+}
+
+template <class T>
+void launch_ne2(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
+  const int nb = ((J.L.N + 8) / 8) * ((J.L.N + 8) / 8);
+  if (zg) k_ne2<T, 8, 8, true, false><<<nb, 256, 0, s>>>(J);
+  else if (pro) k_ne2<T, 8, 8, false, true><<<nb, 256, 0, s>>>(J);
+  else k_ne2<T, 8, 8, false, false><<<nb, 256, 0, s>>>(J);
+}
+template void launch_ne2<double>(const NEJob<double>&, bool, bool, hipStream_t);
+template void launch_ne2<float>(const NEJob<float>&, bool, bool, hipStream_t);
+
+template <class T, bool PACK>
+static void launch_ne2_b_pack(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
+  if (zg) k_ne2_b<T, 8, 8, true, false, PACK><<<nb, 256, 0, s>>>(A);
+  else if (pro) k_ne2_b<T, 8, 8, false, true, PACK><<<nb, 256, 0, s>>>(A);
+  else k_ne2_b<T, 8, 8, false, false, PACK><<<nb, 256, 0, s>>>(A);
+}
+
+template <class T>
+void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
+  if (A.n > 0) launch_ne2_b_pack<T, true>(A, nb, zg, pro, s);
+  else launch_ne2_b_pack<T, false>(A, nb, zg, pro, s);
+}
+template void launch_ne2_b<double>(const JobArg<NEJob<double>>&, int, bool, bool, hipStream_t);
+template void launch_ne2_b<float>(const JobArg<NEJob<float>>&, int, bool, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // k_resid_restrict: F_c = P^T (F - A x) on an 8 x 8 tile of coarse squares
