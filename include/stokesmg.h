@@ -78,13 +78,22 @@ typedef struct {
   int nu_post;    /* smoothing steps after it                                   */
   int gamma;      /* 1 = V-cycle, 2 = W-cycle                                    */
   int n0;         /* cells per side of the coarsest grid (>= 2); solved exactly */
-  int unfused;    /* 0 (default): fused kernels (one launch per smoothing step,
-                     defect + restriction in one launch, the levels with at most
-                     16 squares per side in one single-workgroup launch);
+  int unfused;    /* 0 (default): fused kernels (one or two smoothing steps per
+                     launch, defect + restriction in one launch, the coarsest
+                     levels in one single-workgroup launch);
                      1: one launch per operator application (reference path) */
+  /* Launch schedule of the fused path.  It changes no arithmetic result
+   * beyond rounding order; smg_tune searches it.  0 selects the default.    */
+  int fuse_depth;   /* normal-equation steps per launch on levels with 8 x 8
+                       tiles: 1 or 2 (default 2)                               */
+  int coarse_max_n; /* largest grid (squares per side) of the single-workgroup
+                       coarse kernel (default 8; the coarsest level always)    */
+  int tile_x;       /* squares per tile row of the normal-equation kernels: 8
+                       or 16 (default: 16 for N >= 128, else 8)                */
 } smg_params;
 
-/* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2, fused. */
+/* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2, fused,
+ * default launch schedule. */
 int smg_default_params(smg_params* prm);
 
 /* Thread-local description of the last error (never NULL). */
@@ -269,6 +278,28 @@ int smg_batch_time_kernel(smg_batch_t b, int which, int reps, double* avg_ms, sm
  * are overwritten.  Synchronous.
  */
 int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t s);
+
+/*
+ * Launch-schedule autotuner (the iterate of Section 3 is the same for every
+ * schedule; only its launches differ).  For the n instances (N[k], beta[k])
+ * and the parameters `base` (NULL: defaults; must be fused), every candidate
+ * schedule -- coarse_max_n in {n0, 4, 8, 16} (limits that select the same
+ * levels once), tile_x in {0, 8, 16}, fuse_depth in {1, 2} where it matters
+ * (normal equation, tile_x != 16) -- is set up as a batch (one instance when
+ * n = 1), and `iters` iterates of f = 1, g = 0 are timed with HIP events on s
+ * after three untimed ones, in two passes over all candidates (the faster
+ * time of each counts).
+ * `best` receives `base` with the fastest schedule and best_ms its time per
+ * iterate in milliseconds.  If cap > 0 the first cap candidates tried and
+ * their times go to tried / tried_ms; ntried (may be NULL) receives the
+ * number of candidates timed.  Candidates that cannot be set up on this
+ * device are skipped.  Allocates and frees device memory; synchronous.
+ * Errors: SMG_EINVAL (bad sizes, iters outside 1..500, unfused base),
+ * SMG_EHIP (no candidate could be timed).
+ */
+int smg_tune(int n, const int* N, const double* beta, const smg_params* base, int iters,
+             smg_params* best, double* best_ms, smg_params* tried, double* tried_ms, int cap,
+             int* ntried, smg_stream_t s);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,8 @@ SMOOTHERS = {"ne": 0, "uzawa": 1}
 class SmgParams(C.Structure):
     _fields_ = [("smoother", C.c_int), ("tau", C.c_double), ("sigma", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("gamma", C.c_int), ("n0", C.c_int),
-                ("unfused", C.c_int)]
+                ("unfused", C.c_int), ("fuse_depth", C.c_int), ("coarse_max_n", C.c_int),
+                ("tile_x", C.c_int)]
 
 
 class SmgError(RuntimeError):
@@ -60,6 +61,8 @@ SIGNATURES = {
     "smg_batch_destroy": [P],
     "smg_batch_size": [P],
     "smg_batch_time_kernel": [P, I, I, C.POINTER(D), P],
+    "smg_tune": [I, C.POINTER(I), C.POINTER(D), C.POINTER(SmgParams), I, C.POINTER(SmgParams),
+                 C.POINTER(D), C.POINTER(SmgParams), C.POINTER(D), I, C.POINTER(I), P],
     "smg_batch_solve": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),
                         C.POINTER(I), C.POINTER(D), C.POINTER(I), P],
     "smg_batch_solve_mixed": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),

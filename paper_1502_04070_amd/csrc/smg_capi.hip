@@ -109,6 +109,8 @@ struct smg_hier {
   double* mpart = nullptr;         // pressure-mean partials of the finest level
   bool fused = true;
   bool ne2 = true;                 // pairs of normal-equation steps in one launch (8 x 8 levels)
+  int tile_x = 0;                  // normal-equation tile width (0: by level size)
+  int ne_tx(int N) const { return tile_x ? tile_x : ne_tile_shape(N).tx; }
   std::vector<void*> allocs;
 
   template <class T>
@@ -439,7 +441,8 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     z = false;
   }
   // two steps per launch where the level uses 8 x 8 tiles
-  const bool pair = ne && H->ne2 && ne_tile_shape(L.N).tx == 8;
+  const int tx = H->ne_tx(L.N);
+  const bool pair = ne && H->ne2 && tx == 8;
   for (int k = 0; k < prm.nu_pre;) {
     if (ne) {
       NEJob<T> J{};
@@ -451,7 +454,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.done = done;
       const bool two = pair && k + 1 < prm.nu_pre;
       if (two) launch_ne2<T>(J, z, false, s);
-      else launch_ne<T>(J, z, false, s);
+      else launch_ne<T>(J, z, false, tx, s);
       std::swap(cur, alt);
       k += two ? 2 : 1;
     } else {
@@ -489,7 +492,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     J.done = done;
     const bool two = pair && post >= 2;
     if (two) launch_ne2<T>(J, false, true, s);
-    else launch_ne<T>(J, false, true, s);
+    else launch_ne<T>(J, false, true, tx, s);
     std::swap(cur, alt);
     post -= two ? 2 : 1;
   } else {
@@ -506,7 +509,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.done = done;
       const bool two = pair && k + 1 < post;
       if (two) launch_ne2<T>(J, false, false, s);
-      else launch_ne<T>(J, false, false, s);
+      else launch_ne<T>(J, false, false, tx, s);
       std::swap(cur, alt);
       k += two ? 2 : 1;
     } else {
@@ -700,6 +703,9 @@ int smg_default_params(smg_params* prm) {
   prm->gamma = 1;
   prm->n0 = 2;
   prm->unfused = 0;
+  prm->fuse_depth = 0;
+  prm->coarse_max_n = 0;
+  prm->tile_x = 0;
   return SMG_OK;
 }
 
@@ -717,6 +723,9 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     return fail(SMG_EINVAL, "smoothing steps must be in 0..64");
   if (prm.gamma != 1 && prm.gamma != 2) return fail(SMG_EINVAL, "gamma must be 1 or 2");
   if (prm.n0 < 2 || prm.n0 > 8) return fail(SMG_EINVAL, "n0 must be in 2..8");
+  if (prm.fuse_depth < 0 || prm.fuse_depth > 2) return fail(SMG_EINVAL, "fuse_depth must be 0, 1 or 2");
+  if (prm.coarse_max_n < 0) return fail(SMG_EINVAL, "coarse_max_n must be >= 0");
+  if (prm.tile_x != 0 && prm.tile_x != 8 && prm.tile_x != 16) return fail(SMG_EINVAL, "tile_x must be 0, 8 or 16");
   if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
   int L = 0;
   {
@@ -730,8 +739,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   H->prm = prm;
   H->beta = beta;
   H->fused = prm.unfused == 0;
-  // tuning knob SMG_NE2=0: one launch per normal-equation step everywhere
-  if (const char* ev = std::getenv("SMG_NE2")) H->ne2 = std::atoi(ev) != 0;
+  H->ne2 = prm.fuse_depth != 1;
+  H->tile_x = prm.tile_x;
   H->L = L;
   if (hipGetDevice(&H->device) != hipSuccess) { delete H; return fail(SMG_EHIP, "hipGetDevice"); }
   H->lv.resize(L + 1);
@@ -812,12 +821,10 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, H->device);
     const size_t limit = (size_t)std::max(lds_max, lds_optin);
     H->Lc = -1;
-    // largest grid done by the single-workgroup kernel (tuning knob
-    // SMG_COARSE_MAX_N, default 8 squares per side: from N = 16 on, the grid
-    // kernels with two smoothing steps per launch finish a level sooner than
-    // one workgroup does)
-    int cmax = 8;
-    if (const char* ev = std::getenv("SMG_COARSE_MAX_N")) cmax = std::max(0, std::atoi(ev));
+    // largest grid done by the single-workgroup kernel (default 8 squares per
+    // side: from N = 16 on, the grid kernels with two smoothing steps per
+    // launch finish a level sooner than one workgroup does)
+    const int cmax = prm.coarse_max_n > 0 ? prm.coarse_max_n : 8;
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
       if ((prm.n0 << l) > cmax) break;
       const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));

@@ -29,7 +29,7 @@ template <class T>
 void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zero_guess, bool prolong, hipStream_t s);
 int ne_tiles(int N);
 template <class T>
-void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, hipStream_t s);
+void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, int tile_x, hipStream_t s);
 
 // fused defect and restriction: (cu, cp) = P^T (F - A x), L = fine level
 template <class T>

@@ -347,15 +347,14 @@ static void launch_ne_shape(const NEJob<T>& J, bool zg, bool pro, hipStream_t s)
 }
 
 template <class T>
-void launch_ne(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
-  const TileShape t = ne_tile_shape(J.L.N);
-  if (t.tx == 16)
+void launch_ne(const NEJob<T>& J, bool zg, bool pro, int tx, hipStream_t s) {
+  if ((tx ? tx : ne_tile_shape(J.L.N).tx) == 16)
     launch_ne_shape<T, 16, 8>(J, zg, pro, s);
   else
     launch_ne_shape<T, 8, 8>(J, zg, pro, s);
 }
-template void launch_ne<double>(const NEJob<double>&, bool, bool, hipStream_t);
-template void launch_ne<float>(const NEJob<float>&, bool, bool, hipStream_t);
+template void launch_ne<double>(const NEJob<double>&, bool, bool, int, hipStream_t);
+template void launch_ne<float>(const NEJob<float>&, bool, bool, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // k_ne2: two fused normal-equation steps on a TX x TY tile of squares

@@ -34,13 +34,24 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+SCHEDULE_FIELDS = ("fuse_depth", "coarse_max_n", "tile_x")
+
+
+def _set_schedule(params, schedule):
+    """Launch schedule of the fused kernels (see smg_params); None: defaults."""
+    for k, v in (schedule or {}).items():
+        if k not in SCHEDULE_FIELDS:
+            raise ValueError(f"unknown schedule field {k!r}")
+        setattr(params, k, int(v))
+
+
 class Hierarchy:
     """A multigrid hierarchy of the generalized Stokes system on the unit square
     (uniformly refined same-diagonal grid, Taylor-Hood P2-P1)."""
 
     def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
                  sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
-                 n0: int = 2, fused: bool = True, device=None):
+                 n0: int = 2, fused: bool = True, device=None, schedule: dict | None = None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -52,6 +63,7 @@ class Hierarchy:
             tau = 0.35 if smoother == "ne" else 0.8
         self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma),
                                      int(nu_pre), int(nu_post), int(gamma), int(n0), 0 if fused else 1)
+        _set_schedule(self.params, schedule)
         self.N, self.beta, self.smoother = int(N), float(beta), smoother
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -254,7 +266,8 @@ class Batch:
     instances with equal (N, beta)."""
 
     def __init__(self, Ns, betas, smoother: str = "ne", tau: float | None = None, sigma: float = 0.8,
-                 nu_pre: int = 2, nu_post: int = 2, gamma: int = 1, n0: int = 2):
+                 nu_pre: int = 2, nu_post: int = 2, gamma: int = 1, n0: int = 2,
+                 schedule: dict | None = None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -264,6 +277,7 @@ class Batch:
             tau = 0.35 if smoother == "ne" else 0.8
         self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma), int(nu_pre),
                                      int(nu_post), int(gamma), int(n0), 0)
+        _set_schedule(self.params, schedule)
         n = len(Ns)
         Na = (C.c_int * n)(*[int(v) for v in Ns])
         Ba = (C.c_double * n)(*[float(v) for v in betas])
