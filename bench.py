@@ -254,6 +254,20 @@ def extras():
     out["adjoint_16x_h256"] = {"instances": nb, "unknowns_each": dofs(N), "tol": 1e-10,
                                "forward_ms": 1e3 * t_fwd, "forward_and_gradients_ms": 1e3 * t_all,
                                "ratio": t_all / t_fwd}
+    torch.cuda.empty_cache()
+
+    # implicit Euler: four time steps dt marching together at h = 1/256, f = sin(pi x) sin(pi y)
+    from paper_1502_04070_amd.timestep import BatchImplicitEuler
+    dts = [1e-1, 1e-2, 1e-3, 1e-4]
+    Fs, _ = inputs.smooth_plus_noise(N, seed=0, noise=0.0)
+    Fd = torch.from_numpy(Fs).cuda()
+    te = BatchImplicitEuler([N] * len(dts), dts)
+    te.step([Fd] * len(dts))
+    nsteps = 10
+    infos, dt_s = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
+    out["implicit_euler_4dt_h256"] = {
+        "dts": dts, "steps": nsteps, "tol": 1e-10, "ms_per_step": 1e3 * dt_s / nsteps,
+        "iterations_last_step": [i.iters for i in infos[-1]]}
     return out
 
 
@@ -266,6 +280,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / h=1/512 / adjoint workloads")
     ap.add_argument("--extras-only", action="store_true", help="only the batched / h=1/512 / adjoint workloads")
+    ap.add_argument("--probe", type=int, default=0, metavar="N",
+                    help="only time the fused normal-equation step of one h=1/N instance (no graphs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
@@ -281,6 +297,16 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.probe:
+        N = args.probe
+        B = Batch([N], [1.0])
+        ms = B.time_kernel(0, reps=args.kernel_reps)
+        nbytes = ne_step_bytes(N)
+        print(json.dumps({"probe": {"N": N, "kernel": "fused normal-equation step (default tile)",
+                                    "avg_launch_us": 1e3 * ms, "bytes_per_launch": nbytes,
+                                    "achieved_GBps": nbytes / (ms * 1e-3) / 1e9,
+                                    "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}), flush=True)
         return
     if args.extras_only:
         print(json.dumps({"extras": extras()}), flush=True)

@@ -206,6 +206,20 @@ int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, in
                     smg_stream_t s);
 
 /*
+ * One implicit (backward) Euler step of the time-dependent Stokes problem,
+ * the source of the generalized problem (Section 1: beta grows like 1/dt).
+ * h must have been set up with beta = 1/dt.  With u = u^n on input (boundary
+ * entries ignored) this solves
+ *     calA(beta) x = (M_full f + beta M u^n, M_P g)
+ * for x = (u^{n+1}, p^{n+1}) like smg_solve, from the initial guess
+ * (u^n, p), and writes the result to u and p.  f_nodal: nodal values at all
+ * P2 lattice points, layout of u (NULL: f = 0); g_nodal: P1 nodal values with
+ * int g = 0 (NULL: g = 0).  Status codes as smg_solve.  Synchronous.
+ */
+int smg_implicit_step(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
+                      double* u, double* p, int* iters, double* relres, smg_stream_t s);
+
+/*
  * Single-precision cycle (exposed for testing the FP32 kernels): one iterate
  * as in smg_cycle on float vectors of the same layout, coarsest grid solved
  * in FP64.  In place on (u, p).
@@ -259,6 +273,13 @@ int smg_batch_solve(smg_batch_t b, const double* const* fu, const double* const*
 int smg_batch_solve_mixed(smg_batch_t b, const double* const* fu, const double* const* gp,
                           double rtol, int maxit, double* const* u, double* const* p, int* iters,
                           double* relres, int* status, smg_stream_t s);
+
+/* smg_implicit_step for every instance of a batch (instance k set up with
+ * beta_k = 1/dt_k), solved together; f_nodal / g_nodal may be NULL (all
+ * zero) or hold one pointer per instance (NULL entries: zero). */
+int smg_batch_implicit_step(smg_batch_t b, const double* const* f_nodal, const double* const* g_nodal,
+                            double rtol, int maxit, double* const* u, double* const* p, int* iters,
+                            double* relres, int* status, smg_stream_t s);
 
 /*
  * Batched kernel timing (profiling support): `reps` back-to-back launches of

@@ -61,6 +61,8 @@ SIGNATURES = {
     "smg_batch_destroy": [P],
     "smg_batch_size": [P],
     "smg_batch_time_kernel": [P, I, I, C.POINTER(D), P],
+    "smg_implicit_step": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), P],
+    "smg_batch_implicit_step": [P, P, P, D, I, P, P, P, P, P, P],
     "smg_tune": [I, C.POINTER(I), C.POINTER(D), C.POINTER(SmgParams), I, C.POINTER(SmgParams),
                  C.POINTER(D), C.POINTER(SmgParams), C.POINTER(D), I, C.POINTER(I), P],
     "smg_batch_solve": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),

@@ -1017,6 +1017,29 @@ int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxi
   return run_solve(h, false, fu, gp, rtol, maxit, u, p, iters, relres, history, (hipStream_t)sv);
 }
 
+// Right-hand side of one implicit Euler step in the finest level's t buffer:
+// (M_full f + beta M u, M_P g); the solve copies it to f before t is used.
+static void implicit_rhs(smg_hier* H, const double* f_nodal, const double* g_nodal, const double* u,
+                         hipStream_t s) {
+  Level& T = H->lv[H->L];
+  if (f_nodal) launch_mass_u(T.N, 2, f_nodal, T.t.u, s);
+  else launch_fill(T.t.u, T.n_u, 0.0, s);
+  launch_mass_u_acc(T.N, 0, u, H->beta, T.t.u, s);
+  if (g_nodal) launch_mass_p(T.N, g_nodal, T.t.p, s);
+  else launch_fill(T.t.p, T.n_p, 0.0, s);
+}
+
+int smg_implicit_step(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
+                      double* u, double* p, int* iters, double* relres, smg_stream_t sv) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  if (!u || !p) return fail(SMG_EINVAL, "null vector");
+  HIPCHK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)sv;
+  implicit_rhs(h, f_nodal, g_nodal, u, s);
+  Level& T = h->lv[h->L];
+  return run_solve(h, false, T.t.u, T.t.p, rtol, maxit, u, p, iters, relres, nullptr, s);
+}
+
 int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, int maxit,
                     double* u, double* p, int* iters, double* relres, double* history,
                     smg_stream_t sv) {

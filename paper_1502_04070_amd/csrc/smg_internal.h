@@ -148,6 +148,8 @@ void launch_shat_inv(int N, const T* adinv_host4, T* sinv, hipStream_t s);
 // mode 0: interior rows from interior values; 1: all rows from interior values;
 // 2: interior rows from all values (load vectors of nodal data)
 void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s);
+// y += scale * (M u) on the rows of `mode` (same modes as launch_mass_u)
+void launch_mass_u_acc(int N, int mode, const double* u, double scale, double* y, hipStream_t s);
 void launch_mass_p(int N, const double* g, double* gp, hipStream_t s);
 
 // deterministic dots: which = 0 velocity interior lattice points, 1 pressure

@@ -696,7 +696,7 @@ template void launch_shat_inv<float>(int, const float*, float*, hipStream_t);
 
 template <int CLS>
 __device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int read_all,
-                                          const double* u, double* y) {
+                                          const double* u, double* y, double scale, int acc) {
   using T = double;
   constexpr int DA = CLS & 1, DB = CLS >> 1;
   const int M = 2 * N + 1;
@@ -714,25 +714,32 @@ __device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int
       return ok ? uc[(size_t)bb * M + aa] : 0.0;
     };
     const double v = (interior || rows_all) ? h2 * m_row<CLS, T>(U) : 0.0;
-    y[(size_t)c * M * M + (size_t)b * M + a] = v;
+    const size_t g = (size_t)c * M * M + (size_t)b * M + a;
+    y[g] = acc ? y[g] + scale * v : v;
   }
 }
 
 __global__ __launch_bounds__(256) void k_mass_u(int N, int rows_all, int read_all,
-                                                const double* __restrict__ u, double* y) {
+                                                const double* __restrict__ u, double* y, double scale,
+                                                int acc) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= (N + 1) * (N + 1)) return;
   const int i = e % (N + 1), j = e / (N + 1);
-  mass_node<0>(N, i, j, rows_all, read_all, u, y);
-  mass_node<1>(N, i, j, rows_all, read_all, u, y);
-  mass_node<2>(N, i, j, rows_all, read_all, u, y);
-  mass_node<3>(N, i, j, rows_all, read_all, u, y);
+  mass_node<0>(N, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<1>(N, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<2>(N, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<3>(N, i, j, rows_all, read_all, u, y, scale, acc);
 }
 
 void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s) {
   // mode 0: rows interior, read interior; 1: rows all, read interior; 2: rows interior, read all
   const int n = (N + 1) * (N + 1);
-  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y);
+  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, 1.0, 0);
+}
+
+void launch_mass_u_acc(int N, int mode, const double* u, double scale, double* y, hipStream_t s) {
+  const int n = (N + 1) * (N + 1);
+  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, scale, 1);
 }
 
 // P1 mass: the six triangles around vertex (i, j) of the same-diagonal grid,

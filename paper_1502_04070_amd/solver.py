@@ -254,6 +254,22 @@ class Hierarchy:
         """Iterate to ||F - calA x|| <= rtol ||F||; returns (u, p, SolveInfo)."""
         return self._solve(self.lib.smg_solve, "smg_solve", fu, gp, rtol, maxit, u, p)
 
+    def implicit_step(self, u, p, f_nodal=None, g_nodal=None, rtol=1e-10, maxit=200):
+        """One implicit Euler step with dt = 1 / beta of this hierarchy, in place:
+        (u, p) = (u^n, guess) -> (u^{n+1}, p^{n+1}).  f_nodal: nodal values at all
+        P2 lattice points, g_nodal: P1 nodal values with zero integral."""
+        L = self.L
+        self._chk(L, (u, "u"), (p, "p"))
+        if f_nodal is not None:
+            self._chk(L, (f_nodal, "u"))
+        if g_nodal is not None:
+            self._chk(L, (g_nodal, "p"))
+        it, rel = C.c_int(), C.c_double()
+        code = self.lib.smg_implicit_step(self.h, _ptr(f_nodal), _ptr(g_nodal), float(rtol), int(maxit),
+                                          _ptr(u), _ptr(p), C.byref(it), C.byref(rel), _stream())
+        _lib.check(code, "smg_implicit_step", soft_ok=True)
+        return SolveInfo(_lib.STATUS[code], it.value, rel.value, [])
+
     def solve_mixed(self, fu, gp, rtol=1e-10, maxit=400, u=None, p=None):
         """FP32 cycles inside FP64 iterative refinement."""
         return self._solve(self.lib.smg_solve_mixed, "smg_solve_mixed", fu, gp, rtol, maxit, u, p)
@@ -325,6 +341,25 @@ class Batch:
 
     def solve(self, fus, gps, rtol=1e-8, maxit=200, us=None, ps=None):
         return self._solve(self.lib.smg_batch_solve, "smg_batch_solve", fus, gps, rtol, maxit, us, ps)
+
+    def implicit_step(self, us, ps, f_nodals=None, g_nodals=None, rtol=1e-10, maxit=200):
+        """Hierarchy.implicit_step for every instance (dt_k = 1 / beta_k), in place."""
+        n = self.n
+        for k, h in enumerate(self.instances):
+            h._chk(h.L, (us[k], "u"), (ps[k], "p"))
+            if f_nodals is not None and f_nodals[k] is not None:
+                h._chk(h.L, (f_nodals[k], "u"))
+            if g_nodals is not None and g_nodals[k] is not None:
+                h._chk(h.L, (g_nodals[k], "p"))
+        arr = lambda ts: (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None) for t in ts])
+        it = (C.c_int * n)()
+        rel = (C.c_double * n)()
+        st = (C.c_int * n)()
+        code = self.lib.smg_batch_implicit_step(self.b, arr(f_nodals) if f_nodals is not None else None,
+                                                arr(g_nodals) if g_nodals is not None else None, float(rtol),
+                                                int(maxit), arr(us), arr(ps), it, rel, st, _stream())
+        _lib.check(code, "smg_batch_implicit_step", soft_ok=True)
+        return [SolveInfo(_lib.STATUS[st[k]], it[k], rel[k], []) for k in range(n)]
 
     def solve_mixed(self, fus, gps, rtol=1e-10, maxit=400, us=None, ps=None):
         return self._solve(self.lib.smg_batch_solve_mixed, "smg_batch_solve_mixed", fus, gps, rtol, maxit, us, ps)
