@@ -281,7 +281,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / h=1/512 / adjoint workloads")
     ap.add_argument("--extras-only", action="store_true", help="only the batched / h=1/512 / adjoint workloads")
     ap.add_argument("--probe", type=int, default=0, metavar="N",
-                    help="only time the fused normal-equation step of one h=1/N instance (no graphs)")
+                    help="only time the batched fused normal-equation step at h=1/N (no graphs)")
+    ap.add_argument("--probe-count", type=int, default=1,
+                    help="instances of the probe batch (5: the betas of the main workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
@@ -299,11 +301,12 @@ def main():
         copy_calibration()
         return
     if args.probe:
-        N = args.probe
-        B = Batch([N], [1.0])
+        N, cnt = args.probe, args.probe_count
+        betas = BETAS if cnt == len(BETAS) else [1.0] * cnt
+        B = Batch([N] * cnt, betas)
         ms = B.time_kernel(0, reps=args.kernel_reps)
-        nbytes = ne_step_bytes(N)
-        print(json.dumps({"probe": {"N": N, "kernel": "fused normal-equation step (default tile)",
+        nbytes = ne_step_bytes(N) * cnt
+        print(json.dumps({"probe": {"N": N, "instances": cnt, "kernel": "fused normal-equation step (default tile)",
                                     "avg_launch_us": 1e3 * ms, "bytes_per_launch": nbytes,
                                     "achieved_GBps": nbytes / (ms * 1e-3) / 1e9,
                                     "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}), flush=True)
