@@ -265,6 +265,23 @@ def extras():
     te.step([Fd] * len(dts))
     nsteps = 10
     infos, dt_s = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
+    # damping per level, searched for each beta of the main workload (h = 1/128)
+    from paper_1502_04070_amd import tune as _tune
+    rec = {}
+    F128, G128 = inputs.uniform_f(N_GRID, seed=0)
+    for beta in BETAS:
+        damp, info = _tune.damping_for(N_GRID, beta, factors=(0.8, 0.9, 1.0, 1.1, 1.2))
+        h0 = Hierarchy(N_GRID, beta)
+        h1 = Hierarchy(N_GRID, beta, damping=damp)
+        fu, gp = h0.load(torch.from_numpy(F128).cuda(), torch.from_numpy(G128).cuda())
+        r = {"tau": [round(t, 4) for t in damp["tau"]]}
+        for name, hh in (("default", h0), ("tuned", h1)):
+            hh.solve(fu, gp, rtol=TOL, maxit=500)
+            (_, _, inf), dt_s = _timed(lambda: hh.solve(fu, gp, rtol=TOL, maxit=500))
+            r[name] = {"iterations": inf.iters, "time_to_tol_ms": 1e3 * dt_s}
+        rec[str(beta)] = r
+    out["level_damping_h128"] = rec
+
     out["implicit_euler_4dt_h256"] = {
         "dts": dts, "steps": nsteps, "tol": 1e-10, "ms_per_step": 1e3 * dt_s / nsteps,
         "iterations_last_step": [i.iters for i in infos[-1]]}

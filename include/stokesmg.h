@@ -206,6 +206,18 @@ int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, in
                     smg_stream_t s);
 
 /*
+ * Smoother damping per level (Section 6 remarks that the rates improve
+ * slightly when tau and sigma depend on the level and on beta).  Sets tau and
+ * sigma of `level` (-1: every level) of h; they start at smg_params' tau and
+ * sigma.  The coarsest level (solved exactly) ignores them.  Captured
+ * iterates of h are dropped and captured again by the next solve.  For a
+ * hierarchy of a batch use smg_batch_set_damping.  Errors: SMG_EINVAL
+ * (values not finite and > 0, bad level).
+ */
+int smg_set_damping(smg_t h, int level, double tau, double sigma);
+int smg_get_damping(smg_t h, int level, double* tau, double* sigma);
+
+/*
  * One implicit (backward) Euler step of the time-dependent Stokes problem,
  * the source of the generalized problem (Section 1: beta grows like 1/dt).
  * h must have been set up with beta = 1/dt.  With u = u^n on input (boundary
@@ -273,6 +285,10 @@ int smg_batch_solve(smg_batch_t b, const double* const* fu, const double* const*
 int smg_batch_solve_mixed(smg_batch_t b, const double* const* fu, const double* const* gp,
                           double rtol, int maxit, double* const* u, double* const* p, int* iters,
                           double* relres, int* status, smg_stream_t s);
+
+/* smg_set_damping for instance `instance` (-1: all) of a batch; the
+ * batch's captured iterates are rebuilt by its next solve. */
+int smg_batch_set_damping(smg_batch_t b, int instance, int level, double tau, double sigma);
 
 /* smg_implicit_step for every instance of a batch (instance k set up with
  * beta_k = 1/dt_k), solved together; f_nodal / g_nodal may be NULL (all

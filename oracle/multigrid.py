@@ -44,6 +44,14 @@ class Params:
     nu_pre: int = 2
     nu_post: int = 2
     gamma: int = 1             # 1 = V-cycle, 2 = W-cycle
+    level_tau: tuple | None = None     # damping per level k (index k), replacing tau
+    level_sigma: tuple | None = None   # the same for sigma
+
+    def tau_at(self, k: int) -> float:
+        return self.tau if self.level_tau is None else self.level_tau[k]
+
+    def sigma_at(self, k: int) -> float:
+        return self.sigma if self.level_sigma is None else self.level_sigma[k]
 
     @staticmethod
     def uzawa(nu_pre=3, nu_post=3, gamma=1):
@@ -142,11 +150,15 @@ def uzawa_step(lv: Level, x: np.ndarray, f: np.ndarray, tau: float, sigma: float
     return np.concatenate([u_new, p_new])
 
 
-def smooth(lv: Level, x: np.ndarray, f: np.ndarray, prm: Params) -> np.ndarray:
+def smooth(lv: Level, x: np.ndarray, f: np.ndarray, prm: Params, k: int | None = None) -> np.ndarray:
+    """One smoothing step on level k (the damping of level k when per-level
+    values are given; Section 6 remarks that they may depend on the level)."""
+    tau = prm.tau if k is None else prm.tau_at(k)
+    sigma = prm.sigma if k is None else prm.sigma_at(k)
     if prm.smoother == "ne":
-        return ne_step(lv, x, f, prm.tau)
+        return ne_step(lv, x, f, tau)
     if prm.smoother == "uzawa":
-        return uzawa_step(lv, x, f, prm.tau, prm.sigma)
+        return uzawa_step(lv, x, f, tau, sigma)
     raise ValueError(prm.smoother)
 
 
@@ -166,14 +178,14 @@ def cycle(h: Hierarchy, k: int, x: np.ndarray, f: np.ndarray, prm: Params) -> np
         return h.levels[0].direct_solve(f)
     lv = h.levels[k]
     for _ in range(prm.nu_pre):
-        x = smooth(lv, x, f, prm)
+        x = smooth(lv, x, f, prm, k)
     rc = restrict_residual(h, k, x, f)
     z = np.zeros(h.levels[k - 1].n)
     for _ in range(prm.gamma):
         z = cycle(h, k - 1, z, rc, prm)
     x = x + lv.P @ z
     for _ in range(prm.nu_post):
-        x = smooth(lv, x, f, prm)
+        x = smooth(lv, x, f, prm, k)
     return x
 
 

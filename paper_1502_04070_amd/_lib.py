@@ -61,6 +61,9 @@ SIGNATURES = {
     "smg_batch_destroy": [P],
     "smg_batch_size": [P],
     "smg_batch_time_kernel": [P, I, I, C.POINTER(D), P],
+    "smg_set_damping": [P, I, D, D],
+    "smg_get_damping": [P, I, C.POINTER(D), C.POINTER(D)],
+    "smg_batch_set_damping": [P, I, I, D, D],
     "smg_implicit_step": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), P],
     "smg_batch_implicit_step": [P, P, P, D, I, P, P, P, P, P, P],
     "smg_tune": [I, C.POINTER(I), C.POINTER(D), C.POINTER(SmgParams), I, C.POINTER(SmgParams),

@@ -67,6 +67,7 @@ struct Level {
   Vec<float> x32, f32, t32;
   double* partial = nullptr;  // one double per stencil tile
   int ntiles = 0;
+  double tau = 0.0, sigma = 0.0;  // smoother damping on this level (smg_set_damping)
 };
 
 template <class T> struct Sel;
@@ -289,7 +290,7 @@ void smooth_step(const smg_params& prm, Level& L, Vec<T> x, Vec<T> f, Vec<T> t, 
     B.in_u = t.u; B.in_p = t.p;
     B.base_u = zg ? nullptr : x.u;
     B.base_p = zg ? nullptr : x.p;
-    B.w_u = B.w_p = T(-prm.tau);
+    B.w_u = B.w_p = T(-L.tau);
     B.diag_u = B.diag_p = 1;
     B.out_u = x.u; B.out_p = x.p;
     B.done = done;
@@ -301,7 +302,7 @@ void smooth_step(const smg_params& prm, Level& L, Vec<T> x, Vec<T> f, Vec<T> t, 
     A.in_p = zg ? nullptr : x.p;
     A.rhs_u = f.u;
     A.base_u = zg ? nullptr : x.u;
-    A.w_u = T(prm.tau);
+    A.w_u = T(L.tau);
     A.diag_u = 1;
     A.out_u = t.u;
     A.done = done;
@@ -310,7 +311,7 @@ void smooth_step(const smg_params& prm, Level& L, Vec<T> x, Vec<T> f, Vec<T> t, 
     StencilJob<T> B = job_of<T>(L);
     B.in_u = t.u;
     B.rhs_p = f.p;
-    B.w_p = T(-prm.sigma);
+    B.w_p = T(-L.sigma);
     B.diag_p = 1;
     B.out_p = t.p;
     B.done = done;
@@ -319,7 +320,7 @@ void smooth_step(const smg_params& prm, Level& L, Vec<T> x, Vec<T> f, Vec<T> t, 
     StencilJob<T> C = job_of<T>(L);
     C.in_p = t.p;
     C.base_u = t.u;
-    C.w_u = T(prm.tau);
+    C.w_u = T(L.tau);
     C.diag_u = 1;
     C.rhs_p = t.p;
     C.base_p = zg ? nullptr : x.p;
@@ -407,8 +408,10 @@ void coarse_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hip
   J.fu = f.u; J.fp = f.p;
   J.xu = x.u; J.xp = x.p;
   J.zero_guess = zg ? 1 : 0;
-  J.tau = T(H->prm.tau);
-  J.sigma = T(H->prm.sigma);
+  for (int l = 0; l <= H->Lc; ++l) {
+    J.tau[l] = T(H->lv[l].tau);
+    J.sigma[l] = T(H->lv[l].sigma);
+  }
   J.done = done;
   launch_coarse_cycle<T>(J, s);
 }
@@ -450,7 +453,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.xu = cur.u; J.xp = cur.p;
       J.fu = f.u; J.fp = f.p;
       J.ou = alt.u; J.op = alt.p;
-      J.tau = T(prm.tau);
+      J.tau = T(L.tau);
       J.done = done;
       const bool two = pair && k + 1 < prm.nu_pre;
       if (two) launch_ne2<T>(J, z, false, s);
@@ -488,7 +491,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     J.fu = f.u; J.fp = f.p;
     J.ou = alt.u; J.op = alt.p;
     J.zu = zc.u; J.zp = zc.p;
-    J.tau = T(prm.tau);
+    J.tau = T(L.tau);
     J.done = done;
     const bool two = pair && post >= 2;
     if (two) launch_ne2<T>(J, false, true, s);
@@ -505,7 +508,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.xu = cur.u; J.xp = cur.p;
       J.fu = f.u; J.fp = f.p;
       J.ou = alt.u; J.op = alt.p;
-      J.tau = T(prm.tau);
+      J.tau = T(L.tau);
       J.done = done;
       const bool two = pair && k + 1 < post;
       if (two) launch_ne2<T>(J, false, false, s);
@@ -748,6 +751,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   for (int l = 0; l <= L; ++l) {
     Level& Lv = H->lv[l];
     Lv.N = prm.n0 << l;
+    Lv.tau = prm.tau;
+    Lv.sigma = prm.sigma;
     const int64_t M = 2 * Lv.N + 1;
     Lv.n_u = 2 * M * M;
     Lv.n_p = (int64_t)(Lv.N + 1) * (Lv.N + 1);
@@ -1017,6 +1022,32 @@ int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxi
   return run_solve(h, false, fu, gp, rtol, maxit, u, p, iters, relres, history, (hipStream_t)sv);
 }
 
+int smg_set_damping(smg_t h, int level, double tau, double sigma) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  if (!(tau > 0) || !(sigma > 0) || !std::isfinite(tau) || !std::isfinite(sigma))
+    return fail(SMG_EINVAL, "tau and sigma must be finite and > 0");
+  if (level < -1 || level > h->L) return fail(SMG_EINVAL, "level %d not in -1..%d", level, h->L);
+  for (int l = 0; l <= h->L; ++l)
+    if (level < 0 || l == level) {
+      h->lv[l].tau = tau;
+      h->lv[l].sigma = sigma;
+    }
+  // captured iterates carry the old values in their launch arguments
+  if (h->g64) (void)hipGraphExecDestroy(h->g64);
+  if (h->g32) (void)hipGraphExecDestroy(h->g32);
+  h->g64 = h->g32 = nullptr;
+  return SMG_OK;
+}
+
+int smg_get_damping(smg_t h, int level, double* tau, double* sigma) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!tau || !sigma) return fail(SMG_EINVAL, "null output");
+  *tau = h->lv[level].tau;
+  *sigma = h->lv[level].sigma;
+  return SMG_OK;
+}
+
 // Right-hand side of one implicit Euler step in the finest level's t buffer:
 // (M_full f + beta M u, M_P g); the solve copies it to f before t is used.
 static void implicit_rhs(smg_hier* H, const double* f_nodal, const double* g_nodal, const double* u,
@@ -1072,7 +1103,7 @@ int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t s
     J.in_u = T.t.u; J.in_p = T.t.p;
     J.base_u = T.x.u; J.base_p = T.x.p;
     J.out_u = T.x.u; J.out_p = T.x.p;
-    J.w_u = J.w_p = -h->prm.tau;
+    J.w_u = J.w_p = -T.tau;
     J.diag_u = J.diag_p = 1;
   }
   if (which == 3) J.w_u = J.w_p = -1.0;

@@ -64,7 +64,7 @@ struct CoarseJob {
   T* xu;
   T* xp;                 // iterate of level Lc (global; read unless zero_guess)
   int zero_guess;
-  T tau, sigma;
+  T tau[CC_MAX_LEVELS + 1], sigma[CC_MAX_LEVELS + 1];   // smoother damping per level
   const int* done;
 };
 size_t coarse_cycle_lds(int n0, int Lc, size_t elem);

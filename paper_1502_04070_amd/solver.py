@@ -37,6 +37,15 @@ def _stream():
 SCHEDULE_FIELDS = ("fuse_depth", "coarse_max_n", "tile_x")
 
 
+def _apply_damping(set_level, damping):
+    """damping = {"tau": [per level], "sigma": [per level]} (level 0 first)."""
+    taus, sigmas = damping.get("tau"), damping.get("sigma")
+    n = len(taus) if taus is not None else len(sigmas)
+    for level in range(n):
+        set_level(level, taus[level] if taus is not None else None,
+                  sigmas[level] if sigmas is not None else None)
+
+
 def _set_schedule(params, schedule):
     """Launch schedule of the fused kernels (see smg_params); None: defaults."""
     for k, v in (schedule or {}).items():
@@ -51,7 +60,8 @@ class Hierarchy:
 
     def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
                  sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
-                 n0: int = 2, fused: bool = True, device=None, schedule: dict | None = None):
+                 n0: int = 2, fused: bool = True, device=None, schedule: dict | None = None,
+                 damping: dict | None = None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -73,6 +83,8 @@ class Hierarchy:
         self._owned = True
         self.nlevels = self.lib.smg_num_levels(h)
         self.L = self.nlevels - 1
+        if damping:
+            _apply_damping(self.set_damping, damping)
 
     @classmethod
     def _view(cls, lib, handle, params, N, beta, smoother, device):
@@ -254,6 +266,19 @@ class Hierarchy:
         """Iterate to ||F - calA x|| <= rtol ||F||; returns (u, p, SolveInfo)."""
         return self._solve(self.lib.smg_solve, "smg_solve", fu, gp, rtol, maxit, u, p)
 
+    def set_damping(self, level: int, tau: float | None, sigma: float | None = None):
+        """Smoother damping of one level (-1: all levels); None keeps a value."""
+        if tau is None or sigma is None:
+            t0, s0 = self.damping(max(level, 0))
+            tau = t0 if tau is None else tau
+            sigma = s0 if sigma is None else sigma
+        _lib.check(self.lib.smg_set_damping(self.h, int(level), float(tau), float(sigma)), "smg_set_damping")
+
+    def damping(self, level: int):
+        t, sg = C.c_double(), C.c_double()
+        _lib.check(self.lib.smg_get_damping(self.h, int(level), C.byref(t), C.byref(sg)), "smg_get_damping")
+        return t.value, sg.value
+
     def implicit_step(self, u, p, f_nodal=None, g_nodal=None, rtol=1e-10, maxit=200):
         """One implicit Euler step with dt = 1 / beta of this hierarchy, in place:
         (u, p) = (u^n, guess) -> (u^{n+1}, p^{n+1}).  f_nodal: nodal values at all
@@ -275,6 +300,11 @@ class Hierarchy:
         return self._solve(self.lib.smg_solve_mixed, "smg_solve_mixed", fu, gp, rtol, maxit, u, p)
 
 
+def _fill(h, level, tau, sigma):
+    t0, s0 = h.damping(level)
+    return (t0 if tau is None else tau), (s0 if sigma is None else sigma)
+
+
 class Batch:
     """Many independent instances (sizes N_k = n0 2^L_k, coefficients beta_k)
     solved together: one launch per stage for all of them, one captured graph
@@ -283,7 +313,7 @@ class Batch:
 
     def __init__(self, Ns, betas, smoother: str = "ne", tau: float | None = None, sigma: float = 0.8,
                  nu_pre: int = 2, nu_post: int = 2, gamma: int = 1, n0: int = 2,
-                 schedule: dict | None = None):
+                 schedule: dict | None = None, damping: dict | None = None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -304,6 +334,11 @@ class Batch:
         dev = torch.device("cuda", torch.cuda.current_device())
         self.instances = [Hierarchy._view(self.lib, self.lib.smg_batch_handle(b, k), self.params, int(Ns[k]),
                                           float(betas[k]), smoother, dev) for k in range(n)]
+        if damping:
+            # one damping table for every instance (levels beyond an instance's depth are skipped)
+            for k, h in enumerate(self.instances):
+                _apply_damping(lambda lv, t, sg, k=k, h=h: self.set_damping(k, lv, *_fill(h, lv, t, sg))
+                               if lv <= h.L else None, damping)
 
     def __len__(self):
         return self.n
@@ -341,6 +376,11 @@ class Batch:
 
     def solve(self, fus, gps, rtol=1e-8, maxit=200, us=None, ps=None):
         return self._solve(self.lib.smg_batch_solve, "smg_batch_solve", fus, gps, rtol, maxit, us, ps)
+
+    def set_damping(self, instance: int, level: int, tau: float, sigma: float):
+        """Smoother damping of one level (-1: all) of one instance (-1: all)."""
+        _lib.check(self.lib.smg_batch_set_damping(self.b, int(instance), int(level), float(tau), float(sigma)),
+                   "smg_batch_set_damping")
 
     def implicit_step(self, us, ps, f_nodals=None, g_nodals=None, rtol=1e-10, maxit=200):
         """Hierarchy.implicit_step for every instance (dt_k = 1 / beta_k), in place."""

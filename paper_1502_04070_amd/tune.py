@@ -1,4 +1,4 @@
-"""Launch-schedule autotuning with a JSON cache.
+"""Launch-schedule and damping autotuning with a JSON cache.
 
 The schedule of the fused kernels (normal-equation steps per launch, the
 levels of the single-workgroup coarse kernel, the tile width) changes no
@@ -13,10 +13,11 @@ import ctypes as C
 import json
 import os
 
+import numpy as np
 import torch
 
-from . import _lib
-from .solver import SCHEDULE_FIELDS, _stream
+from . import _lib, inputs
+from .solver import SCHEDULE_FIELDS, Hierarchy, _stream
 
 MAX_CANDIDATES = 32
 
@@ -89,3 +90,63 @@ def schedule_for(Ns, betas, smoother="ne", nu_pre=2, nu_post=2, gamma=1, n0=2, r
         _store(db)
     rec = db[key]
     return dict(rec["schedule"]), rec
+
+
+# ---------------------------------------------------------------------------
+# damping per level (Section 6 remarks that the rates improve slightly when
+# tau and sigma depend on the level and on beta)
+# ---------------------------------------------------------------------------
+
+def _rate(h, fu, gp, rtol, maxit):
+    _, _, info = h.solve(fu, gp, rtol=rtol, maxit=maxit)
+    if info.status != "ok" or info.iters == 0:
+        return float("inf"), info.iters
+    return float(info.relres) ** (1.0 / info.iters), info.iters
+
+
+def tune_damping(N, beta, smoother="ne", nu_pre=2, nu_post=2, gamma=1, n0=2, rtol=1e-8, maxit=400,
+                 factors=(0.8, 0.9, 1.0, 1.1, 1.2), sweeps=1, seed=0):
+    """Coordinate search over the damping of every level above the coarsest
+    (finest first): tau for the normal-equation smoother, tau and sigma for
+    the Uzawa smoother, each scaled by the given factors around its current
+    value.  The objective is the mean residual reduction per iterate of a
+    solve from zero with synthetic data (f, g iid N(0, 1), seed).  Returns
+    {"tau": [...], "sigma": [...], "rate": q, "iterations": n,
+    "rate_default": q0, "iterations_default": n0}, level 0 first."""
+    h = Hierarchy(N, beta, smoother=smoother, nu_pre=nu_pre, nu_post=nu_post, gamma=gamma, n0=n0)
+    F, G = inputs.normal_fg(N, seed)
+    Gd = torch.from_numpy(G).cuda()
+    h.project_mean(Gd)
+    fu, gp = h.load(torch.from_numpy(F).cuda(), Gd)
+    taus = [h.damping(l)[0] for l in range(h.nlevels)]
+    sigmas = [h.damping(l)[1] for l in range(h.nlevels)]
+    q0, it0 = _rate(h, fu, gp, rtol, maxit)
+    best_q, best_it = q0, it0
+    for _ in range(sweeps):
+        for level in range(h.L, 0, -1):
+            t0, s0 = taus[level], sigmas[level]
+            pairs = [(t0 * a, s0) for a in factors] if smoother == "ne" else \
+                [(t0 * a, s0 * b) for a in factors for b in factors]
+            for t, sg in pairs:
+                if t == t0 and sg == s0:
+                    continue
+                h.set_damping(level, t, sg)
+                q, it = _rate(h, fu, gp, rtol, maxit)
+                if q < best_q:
+                    best_q, best_it = q, it
+                    taus[level], sigmas[level] = t, sg
+            h.set_damping(level, taus[level], sigmas[level])
+    return {"tau": taus, "sigma": sigmas, "rate": best_q, "iterations": best_it,
+            "rate_default": q0, "iterations_default": it0}
+
+
+def damping_for(N, beta, smoother="ne", nu_pre=2, nu_post=2, gamma=1, n0=2, retune=False, **kw):
+    """The cached damping table for (N, beta, smoother, cycle), tuned first when missing."""
+    key = "damping|" + _key([N], smoother, nu_pre, nu_post, gamma, n0) + f"|beta={float(beta)!r}"
+    db = _load()
+    if retune or key not in db:
+        db[key] = tune_damping(N, beta, smoother=smoother, nu_pre=nu_pre, nu_post=nu_post, gamma=gamma,
+                               n0=n0, **kw)
+        _store(db)
+    rec = db[key]
+    return {"tau": rec["tau"], "sigma": rec["sigma"]}, rec

@@ -166,3 +166,35 @@ def test_tables_2_3_level4_band(ib):
     assert _band(n_ne, gne[0]), (beta, n_ne, gne)
     assert _band(n_uz, guz[0]), (beta, n_uz, guz)
     assert n_uz < n_ne                                 # Uzawa converges faster (Section 6)
+
+
+def test_level_damping_acts_on_its_own_level():
+    """Per-level damping (Section 6 remarks that the rates improve when tau depends
+    on the level).  With x = L^{-1/2} v, v an eigenvector of the symmetric
+    L^{-1/2} calA L^{-1/2} with eigenvalue lambda, one normal-equation step with
+    f = 0 multiplies x by 1 - tau lambda^2.  A two-level iterate with nu_pre = 1,
+    nu_post = 0 therefore maps x to (1 - tau_top lambda^2) C x (C the coarse-grid
+    correction), whatever the coarsest level's value (it is solved exactly)."""
+    h = mg.Hierarchy("same_diag", 1, 10.0, n0=2)
+    lv = h.top
+    s = np.sqrt(lv.Ldiag)
+    Ks = lv.calA.toarray() / s[:, None] / s[None, :]
+    w, V = sl.eigh(Ks)
+    k = int(np.argmax(np.abs(w)))
+    lam, x = w[k], V[:, k] / s
+    out = {}
+    for t_top, t_coarse in ((0.2, 0.9), (0.35, 0.1)):
+        prm = mg.Params("ne", 0.5, 0.8, 1, 0, 1, level_tau=(t_coarse, t_top))
+        out[t_top] = mg.cycle(h, 1, x, np.zeros(lv.n), prm) / (1 - t_top * lam ** 2)
+    a, b = out[0.2], out[0.35]
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
+    # the same values on every level reproduce the scalar damping exactly
+    h3 = mg.Hierarchy("same_diag", 2, 10.0, n0=2)
+    f = _rhs(h3.top, 5)
+    x0 = np.zeros(h3.top.n)
+    y1 = mg.cycle(h3, 2, x0, f, mg.Params())
+    y2 = mg.cycle(h3, 2, x0, f, mg.Params(level_tau=(0.35, 0.35, 0.35)))
+    assert np.array_equal(y1, y2)
+    # a middle level's value enters the iterate
+    y3 = mg.cycle(h3, 2, x0, f, mg.Params(level_tau=(0.35, 0.2, 0.35)))
+    assert np.linalg.norm(y3 - y1) > 1e-6 * np.linalg.norm(y1)
