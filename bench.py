@@ -305,8 +305,9 @@ def main():
                     help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(independent instances would be spread over GPUs, a single large one split into strips "
+              "with halo exchanges)", file=sys.stderr)
         sys.exit(2)
 
     import torch
