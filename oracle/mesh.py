@@ -9,7 +9,7 @@ Paper: Section 6 takes Omega = (0,1)^2 and builds the grid levels k = 1, 2, ...
 from a coarsest grid of 8 triangles by uniform refinement (each triangle is
 cut into four).  Section 2 uses that the resulting discrete spaces are nested.
 
-Two coarse meshes are provided:
+Three coarse meshes are provided:
   * ``same_diag(n0)``: n0 x n0 squares, every square cut by the diagonal from
     its lower-left to its upper-right corner.  Refining it once gives
     ``same_diag(2 n0)`` (checked in the tests).
@@ -18,6 +18,10 @@ Two coarse meshes are provided:
     diagonals all meet in the centre.  This is the reading of the paper's
     (missing) coarse-grid figure that satisfies its requirement that every
     element has a vertex inside the domain (Section 2, Taylor-Hood stability).
+  * ``l_shape(n0)``: the same-diagonal grid on the L-shaped domain
+    (0,1)^2 minus [1/2,1]^2 (n0 even), a non-convex domain (Section 1: the
+    method applies there, the analysis does not).  Refining it gives
+    ``l_shape(2 n0)``.
 """
 from __future__ import annotations
 
@@ -77,11 +81,22 @@ class Mesh:
         """(nt, 6) P2 node indices per triangle: v0, v1, v2, m01, m12, m20."""
         return np.hstack([self.tris, self.nv + self.tri_edges])
 
+    def boundary_edges(self) -> np.ndarray:
+        """True for the edges that belong to exactly one triangle."""
+        return np.bincount(self.tri_edges.ravel(), minlength=self.ne) == 1
+
     def boundary_mask(self, coords: np.ndarray) -> np.ndarray:
-        """True for points on the boundary of the unit square."""
-        x, y = coords[:, 0], coords[:, 1]
-        eps = 1e-12
-        return (np.abs(x) < eps) | (np.abs(x - 1) < eps) | (np.abs(y) < eps) | (np.abs(y - 1) < eps)
+        """True for the boundary nodes among the vertices (coords = pts) or the
+        P2 nodes (coords = p2_coords()): vertices of boundary edges and
+        midpoints of boundary edges."""
+        be = self.boundary_edges()
+        bv = np.zeros(self.nv, dtype=bool)
+        bv[self.edges[be].ravel()] = True
+        if len(coords) == self.nv:
+            return bv
+        if len(coords) == self.nv + self.ne:
+            return np.concatenate([bv, be])
+        raise ValueError("coords must be the mesh vertices or its P2 nodes")
 
     def areas(self) -> np.ndarray:
         p, t = self.pts, self.tris
@@ -104,6 +119,29 @@ def same_diag(n0: int) -> Mesh:
             tris.append((a, b, c))
             tris.append((a, c, d))
     return Mesh(pts, tris)
+
+
+def l_shape(n0: int) -> Mesh:
+    """The same-diagonal n0 x n0 grid without the squares in [1/2, 1]^2 (n0 even)."""
+    if n0 < 2 or n0 % 2:
+        raise ValueError("n0 must be even and >= 2")
+    xs = np.arange(n0 + 1) / n0
+    vid = lambda i, j: j * (n0 + 1) + i
+    tris = []
+    for j in range(n0):
+        for i in range(n0):
+            if 2 * i >= n0 and 2 * j >= n0:
+                continue
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    tris = np.array(tris)
+    used = np.unique(tris)
+    new_id = np.full((n0 + 1) ** 2, -1)
+    new_id[used] = np.arange(len(used))
+    X, Y = np.meshgrid(xs, xs)
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)[used]
+    return Mesh(pts, new_id[tris])
 
 
 def union_jack() -> Mesh:
@@ -150,6 +188,8 @@ def hierarchy(kind: str, levels: int, n0: int = 2) -> list[Mesh]:
         meshes = [same_diag(n0)]
     elif kind == "union_jack":
         meshes = [union_jack()]
+    elif kind == "l_shape":
+        meshes = [l_shape(n0)]
     else:
         raise ValueError(kind)
     for _ in range(levels):

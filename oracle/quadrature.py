@@ -123,8 +123,9 @@ def l2_errors(disc, uh, ph, u_exact, p_exact, grad_u_exact, n=8):
         eh1 += np.sum(area[:, None] * w[None] * np.sum((GU[:, :, c, :] - guq) ** 2, axis=-1))
     phq = np.einsum("ti,qi->tq", ph[mesh.tris], lam)
     wq = area[:, None] * w[None]
-    mean_ex = np.sum(wq * Pex)
-    mean_h = np.sum(wq * phq)
+    vol = np.sum(wq)                       # |Omega| (1 on the unit square, 3/4 on the L-shape)
+    mean_ex = np.sum(wq * Pex) / vol
+    mean_h = np.sum(wq * phq) / vol
     ep2 = np.sum(wq * ((Pex - mean_ex) - (phq - mean_h)) ** 2)
     return np.sqrt(eu2), np.sqrt(eh1), np.sqrt(ep2)
 

@@ -22,7 +22,9 @@ def _p1_lattice(disc, N):
 
 
 def level_N(disc):
-    return int(round(np.sqrt(disc.mesh.nt / 2)))
+    """Squares per side: the inverse of the smallest positive vertex coordinate."""
+    x = disc.mesh.pts[:, 0]
+    return int(round(1.0 / x[x > 1e-14].min()))
 
 
 def to_lattice(disc, x):
