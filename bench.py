@@ -264,7 +264,13 @@ def extras():
     te = BatchImplicitEuler([N] * len(dts), dts)
     te.step([Fd] * len(dts))
     nsteps = 10
-    infos, dt_s = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
+    infos, t_steps = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
+    out["implicit_euler_4dt_h256"] = {
+        "dts": dts, "steps": nsteps, "tol": 1e-10, "ms_per_step": 1e3 * t_steps / nsteps,
+        "iterations_last_step": [i.iters for i in infos[-1]]}
+    del te
+    torch.cuda.empty_cache()
+
     # damping per level, searched for each beta of the main workload (h = 1/128)
     from paper_1502_04070_amd import tune as _tune
     rec = {}
@@ -282,9 +288,23 @@ def extras():
         rec[str(beta)] = r
     out["level_damping_h128"] = rec
 
-    out["implicit_euler_4dt_h256"] = {
-        "dts": dts, "steps": nsteps, "tol": 1e-10, "ms_per_step": 1e3 * dt_s / nsteps,
-        "iterations_last_step": [i.iters for i in infos[-1]]}
+    # the L-shaped domain at h = 1/256 (three quarters of the square's
+    # unknowns), f iid U[-1, 1], g = 0, NE V(2,2) to 1e-8, next to the unit square
+    N = 256
+    F, G = inputs.uniform_f(N, seed=0)
+    rec = {"tol": TOL}
+    for beta in (1.0, 1e4):
+        r = {}
+        for dom in ("l_shape", "square"):
+            hh = Hierarchy(N, beta, domain=dom)
+            fu, gp = hh.load(torch.from_numpy(F).cuda(), torch.from_numpy(G).cuda())
+            hh.solve(fu, gp, rtol=TOL, maxit=500)
+            (_, _, inf), t_s = _timed(lambda: hh.solve(fu, gp, rtol=TOL, maxit=500))
+            assert inf.status == "ok", inf
+            r[dom] = {"iterations": inf.iters, "time_to_tol_ms": 1e3 * t_s}
+            del hh
+        rec[f"beta={beta:g}"] = r
+    out["l_shape_h256"] = rec
     return out
 
 

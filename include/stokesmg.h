@@ -90,7 +90,16 @@ typedef struct {
                        coarse kernel (default 8; the coarsest level always)    */
   int tile_x;       /* squares per tile row of the normal-equation kernels: 8
                        or 16 (default: 16 for N >= 128, else 8)                */
+  int domain;       /* SMG_DOMAIN_SQUARE (default): the unit square;
+                       SMG_DOMAIN_LSHAPE: the unit square without [1/2, 1]^2, a
+                       non-convex domain (Section 1: the method applies, the
+                       analysis does not); needs an even n0.  The layouts stay
+                       those of the square: entries at points outside the
+                       domain are never read, and every entry point writes zero
+                       there or leaves them as they were.                      */
 } smg_params;
+
+enum { SMG_DOMAIN_SQUARE = 0, SMG_DOMAIN_LSHAPE = 1 };
 
 /* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2, fused,
  * default launch schedule. */
@@ -242,7 +251,8 @@ int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
 /*
  * Deterministic dot products on a level (device result in out[0]):
  *   which = 0: sum over both velocity components at interior lattice points,
- *   which = 1: sum over all pressure nodes.
+ *   which = 1: sum over all pressure nodes (of the domain: on the L-shaped
+ *   domain points outside it are skipped in both sums).
  */
 int smg_dot(smg_t h, int level, int which, const double* a, const double* b, double* out,
             smg_stream_t s);

@@ -15,13 +15,14 @@ SMG_OK = 0
 STATUS = {0: "ok", -1: "einval", -2: "ehip", -3: "enomem", -4: "esingular",
           1: "noconv", 2: "diverged", 3: "nonfinite"}
 SMOOTHERS = {"ne": 0, "uzawa": 1}
+DOMAINS = {"square": 0, "l_shape": 1}
 
 
 class SmgParams(C.Structure):
     _fields_ = [("smoother", C.c_int), ("tau", C.c_double), ("sigma", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("gamma", C.c_int), ("n0", C.c_int),
                 ("unfused", C.c_int), ("fuse_depth", C.c_int), ("coarse_max_n", C.c_int),
-                ("tile_x", C.c_int)]
+                ("tile_x", C.c_int), ("domain", C.c_int)]
 
 
 class SmgError(RuntimeError):

@@ -111,6 +111,7 @@ struct smg_hier {
   bool fused = true;
   bool ne2 = true;                 // pairs of normal-equation steps in one launch (8 x 8 levels)
   int tile_x = 0;                  // normal-equation tile width (0: by level size)
+  int dom = SMG_DOM_SQUARE;        // domain of the grid (SMG_DOM_*)
   int ne_tx(int N) const { return tile_x ? tile_x : ne_tile_shape(N).tx; }
   std::vector<void*> allocs;
 
@@ -137,9 +138,10 @@ namespace {
 // coefficients (Section 2 matrices on a level, Section 6 diagonal)
 // ---------------------------------------------------------------------------
 
-void make_coef(int N, double beta, LevelCoef<double>& c, LevelCoef<float>& c32) {
+void make_coef(int N, int dom, double beta, LevelCoef<double>& c, LevelCoef<float>& c32) {
   const double h = 1.0 / N, bh2 = beta * h * h;
   c.N = c32.N = N;
+  c.dom = c32.dom = dom;
   c.h = h;
   c32.h = (float)h;
   for (int k = 0; k < 4; ++k) {
@@ -159,16 +161,14 @@ void host_apply(int N, const LevelCoef<T>& c, const T* u, const T* p, T* yu, T* 
   const int M = 2 * N + 1, NP = N + 1;
   const T h = c.h;
   auto Ug = [&](int comp, int a, int b) -> T {
-    return (a > 0 && a < 2 * N && b > 0 && b < 2 * N) ? u[(size_t)comp * M * M + (size_t)b * M + a] : T(0);
+    return dom_u(N, c.dom, a, b) ? u[(size_t)comp * M * M + (size_t)b * M + a] : T(0);
   };
-  auto Pg = [&](int i, int j) -> T {
-    return (i >= 0 && i <= N && j >= 0 && j <= N) ? p[(size_t)j * NP + i] : T(0);
-  };
+  auto Pg = [&](int i, int j) -> T { return dom_p(N, c.dom, i, j) ? p[(size_t)j * NP + i] : T(0); };
   for (int comp = 0; comp < 2; ++comp)
     for (int b = 0; b < M; ++b)
       for (int a = 0; a < M; ++a) {
         T y = T(0);
-        if (a > 0 && a < 2 * N && b > 0 && b < 2 * N) {
+        if (dom_u(N, c.dom, a, b)) {
           const int cls = (a & 1) + 2 * (b & 1), i = a >> 1, j = b >> 1;
           auto U = [&](int da, int db) -> T { return Ug(comp, a + da, b + db); };
           auto C = [&](int g) -> T { return c.acoef[cls][g]; };
@@ -186,15 +186,8 @@ void host_apply(int N, const LevelCoef<T>& c, const T* u, const T* p, T* yu, T* 
     for (int i = 0; i < NP; ++i) {
       auto U0 = [&](int da, int db) -> T { return Ug(0, 2 * i + da, 2 * j + db); };
       auto U1 = [&](int da, int db) -> T { return Ug(1, 2 * i + da, 2 * j + db); };
-      yp[(size_t)j * NP + i] = h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+      yp[(size_t)j * NP + i] = dom_p(N, c.dom, i, j) ? h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
     }
-}
-
-double p1_weight_host(int N, int i, int j) {
-  const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
-  if (!bi && !bj) return 1.0;
-  if (bi != bj) return 0.5;
-  return (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
 }
 
 // Bordered coarsest-grid matrix [[A, B^T, 0], [B, 0, m], [0, m^T, 0]] in the
@@ -216,10 +209,18 @@ int build_coarse_inverse(int N0, const LevelCoef<double>& c, std::vector<double>
   const double h2 = 1.0 / ((double)N0 * N0);
   for (int j = 0; j < NP; ++j)
     for (int i = 0; i < NP; ++i) {
-      const double m = h2 * p1_weight_host(N0, i, j);
+      const double m = h2 * p1_count_w(N0, c.dom, i, j);
       A[(size_t)(2 * nu + j * NP + i) * nc + (nc - 1)] = m;
       A[(size_t)(nc - 1) * nc + (2 * nu + j * NP + i)] = m;
     }
+  // unknowns outside the domain (lattice points and vertices of the removed
+  // part) are decoupled: an identity row and column keep them at zero
+  for (int k = 0; k < 2 * nu; ++k) {
+    const int q = k % nu;
+    if (!dom_u(N0, c.dom, 1 + q % ni, 1 + q / ni)) A[(size_t)k * nc + k] = 1.0;
+  }
+  for (int k = 0; k < NP * NP; ++k)
+    if (!dom_p(N0, c.dom, k % NP, k / NP)) A[(size_t)(2 * nu + k) * nc + (2 * nu + k)] = 1.0;
   double amax = 0.0;
   for (double v : A) amax = std::max(amax, std::fabs(v));
   // LU with partial pivoting, then solve for the identity
@@ -342,7 +343,7 @@ template <class T>
 void cycle_rec(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
   Level& L = H->lv[l];
   if (l == 0) {
-    launch_coarse_solve<T>(L.N, H->nc, H->cinv, f.u, f.p, x.u, x.p, done, s);
+    launch_coarse_solve<T>(L.N, H->dom, H->nc, H->cinv, f.u, f.p, x.u, x.p, done, s);
     return;
   }
   const smg_params& prm = H->prm;
@@ -365,9 +366,9 @@ void cycle_rec(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done,
   launch_stencil<T>(R, ROWS_UP, s);
   Level& C = H->lv[l - 1];
   Vec<T> xc = Sel<T>::x(C), fc = Sel<T>::f(C);
-  launch_restrict<T>(C.N, t.u, t.p, fc.u, fc.p, nullptr, nullptr, done, s);
+  launch_restrict<T>(C.N, H->dom, t.u, t.p, fc.u, fc.p, nullptr, nullptr, done, s);
   for (int g = 0; g < prm.gamma; ++g) cycle_rec<T>(H, l - 1, xc, fc, g == 0, done, s);
-  launch_prolong_add<T>(C.N, xc.u, xc.p, x.u, x.p, done, s);
+  launch_prolong_add<T>(C.N, H->dom, xc.u, xc.p, x.u, x.p, done, s);
   for (int k = 0; k < prm.nu_post; ++k) smooth_step<T>(prm, L, x, f, t, false, done, s);
 }
 
@@ -499,7 +500,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     std::swap(cur, alt);
     post -= two ? 2 : 1;
   } else {
-    launch_prolong_add<T>(C.N, zc.u, zc.p, cur.u, cur.p, done, s);
+    launch_prolong_add<T>(C.N, H->dom, zc.u, zc.p, cur.u, cur.p, done, s);
   }
   for (int k = 0; k < post;) {
     if (ne) {
@@ -536,7 +537,7 @@ void top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStr
 }
 
 void project_mean(smg_hier* H, int l, double* p, const int* done, hipStream_t s) {
-  launch_project_mean(H->lv[l].N, p, H->red, done, s);
+  launch_project_mean(H->lv[l].N, H->dom, p, H->red, done, s);
 }
 
 // residual of the finest level: optional write, partial sums in L.partial
@@ -563,7 +564,7 @@ void finish_iter(smg_hier* H, double* ru, double* rp, const int* done, hipStream
   R.mean_partial = H->mpart;
   R.done = done;
   launch_stencil<double>(R, ROWS_UP, s);
-  launch_project_check(H->mpart, T.partial, T.ntiles, T.N, T.x.p, H->st, H->hist, s);
+  launch_project_check(H->mpart, T.partial, T.ntiles, T.N, H->dom, T.x.p, H->st, H->hist, s);
 }
 
 // one FP64 iterate of the solve loop on the internal finest-level vectors
@@ -645,8 +646,8 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
   init.tol2 = rtol * rtol;
   *H->st_host = init;
   HIPCHK(hipMemcpyAsync(H->st, H->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
-  launch_dot(T.N, 0, T.f.u, T.f.u, H->red, H->fdots, s);
-  launch_dot(T.N, 1, T.f.p, T.f.p, H->red, H->fdots + 1, s);
+  launch_dot(T.N, H->dom, 0, T.f.u, T.f.u, H->red, H->fdots, s);
+  launch_dot(T.N, H->dom, 1, T.f.p, T.f.p, H->red, H->fdots + 1, s);
   top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, mixed ? T.t.u : nullptr, mixed ? T.t.p : nullptr,
                nullptr, s);
   launch_init_state(T.partial, T.ntiles, H->fdots, H->st, s);
@@ -709,6 +710,7 @@ int smg_default_params(smg_params* prm) {
   prm->fuse_depth = 0;
   prm->coarse_max_n = 0;
   prm->tile_x = 0;
+  prm->domain = SMG_DOM_SQUARE;
   return SMG_OK;
 }
 
@@ -729,6 +731,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   if (prm.fuse_depth < 0 || prm.fuse_depth > 2) return fail(SMG_EINVAL, "fuse_depth must be 0, 1 or 2");
   if (prm.coarse_max_n < 0) return fail(SMG_EINVAL, "coarse_max_n must be >= 0");
   if (prm.tile_x != 0 && prm.tile_x != 8 && prm.tile_x != 16) return fail(SMG_EINVAL, "tile_x must be 0, 8 or 16");
+  if (prm.domain != SMG_DOM_SQUARE && prm.domain != SMG_DOM_LSHAPE) return fail(SMG_EINVAL, "unknown domain %d", prm.domain);
+  if (prm.domain == SMG_DOM_LSHAPE && prm.n0 % 2) return fail(SMG_EINVAL, "the L-shaped domain needs an even n0");
   if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
   int L = 0;
   {
@@ -743,6 +747,7 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   H->beta = beta;
   H->fused = prm.unfused == 0;
   H->ne2 = prm.fuse_depth != 1;
+  H->dom = prm.domain;
   H->tile_x = prm.tile_x;
   H->L = L;
   if (hipGetDevice(&H->device) != hipSuccess) { delete H; return fail(SMG_EHIP, "hipGetDevice"); }
@@ -756,7 +761,7 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     const int64_t M = 2 * Lv.N + 1;
     Lv.n_u = 2 * M * M;
     Lv.n_p = (int64_t)(Lv.N + 1) * (Lv.N + 1);
-    make_coef(Lv.N, beta, Lv.c64, Lv.c32);
+    make_coef(Lv.N, H->dom, beta, Lv.c64, Lv.c32);
     const int64_t nv = Lv.n_u + Lv.n_p;
     double* b64 = H->alloc<double>(3 * nv);
     float* b32 = H->alloc<float>(3 * nv);
@@ -800,8 +805,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   hipStream_t s = H->cap_stream;
   for (int l = 0; l <= L; ++l) {
     Level& Lv = H->lv[l];
-    launch_shat_inv<double>(Lv.N, Lv.c64.adinv, const_cast<double*>(Lv.c64.sinv), s);
-    launch_shat_inv<float>(Lv.N, Lv.c32.adinv, const_cast<float*>(Lv.c32.sinv), s);
+    launch_shat_inv<double>(Lv.N, H->dom, Lv.c64.adinv, const_cast<double*>(Lv.c64.sinv), s);
+    launch_shat_inv<float>(Lv.N, H->dom, Lv.c32.adinv, const_cast<float*>(Lv.c32.sinv), s);
     for (int k = 0; k < 1; ++k) {
       launch_fill(Lv.x.u, 3 * (Lv.n_u + Lv.n_p), 0.0, s);
       launch_fill_f32(Lv.x32.u, 3 * (Lv.n_u + Lv.n_p), 0.0f, s);
@@ -888,11 +893,11 @@ int smg_load(smg_t h, int level, const double* f_nodal, const double* g_nodal, d
   const int N = h->lv[level].N;
   if (fu) {
     if (!f_nodal) return fail(SMG_EINVAL, "null f_nodal");
-    launch_mass_u(N, 2, f_nodal, fu, s);
+    launch_mass_u(N, h->dom, 2, f_nodal, fu, s);
   }
   if (gp) {
     if (!g_nodal) return fail(SMG_EINVAL, "null g_nodal");
-    launch_mass_p(N, g_nodal, gp, s);
+    launch_mass_p(N, h->dom, g_nodal, gp, s);
   }
   return launch_status("smg_load");
 }
@@ -901,7 +906,7 @@ int smg_mass(smg_t h, int level, int all_nodes, const double* u, double* y, smg_
   int rc = check_level(h, level);
   if (rc) return rc;
   if (!u || !y) return fail(SMG_EINVAL, "null vector");
-  launch_mass_u(h->lv[level].N, all_nodes ? 1 : 0, u, y, (hipStream_t)sv);
+  launch_mass_u(h->lv[level].N, h->dom, all_nodes ? 1 : 0, u, y, (hipStream_t)sv);
   return launch_status("smg_mass");
 }
 
@@ -909,7 +914,7 @@ int smg_pressure_mass(smg_t h, int level, const double* g, double* gp, smg_strea
   int rc = check_level(h, level);
   if (rc) return rc;
   if (!g || !gp) return fail(SMG_EINVAL, "null vector");
-  launch_mass_p(h->lv[level].N, g, gp, (hipStream_t)sv);
+  launch_mass_p(h->lv[level].N, h->dom, g, gp, (hipStream_t)sv);
   return launch_status("smg_pressure_mass");
 }
 
@@ -956,7 +961,7 @@ int smg_restrict(smg_t h, int fine_level, const double* ru, const double* rp, do
   if (rc) return rc;
   if (fine_level < 1) return fail(SMG_EINVAL, "restriction needs fine_level >= 1");
   if (!ru || !rp || !rcu || !rcp) return fail(SMG_EINVAL, "null vector");
-  launch_restrict<double>(h->lv[fine_level - 1].N, ru, rp, rcu, rcp, nullptr, nullptr, nullptr,
+  launch_restrict<double>(h->lv[fine_level - 1].N, h->dom, ru, rp, rcu, rcp, nullptr, nullptr, nullptr,
                           (hipStream_t)sv);
   return launch_status("smg_restrict");
 }
@@ -967,7 +972,7 @@ int smg_prolong_add(smg_t h, int fine_level, const double* zcu, const double* zc
   if (rc) return rc;
   if (fine_level < 1) return fail(SMG_EINVAL, "prolongation needs fine_level >= 1");
   if (!zcu || !zcp || !u || !p) return fail(SMG_EINVAL, "null vector");
-  launch_prolong_add<double>(h->lv[fine_level - 1].N, zcu, zcp, u, p, nullptr, (hipStream_t)sv);
+  launch_prolong_add<double>(h->lv[fine_level - 1].N, h->dom, zcu, zcp, u, p, nullptr, (hipStream_t)sv);
   return launch_status("smg_prolong_add");
 }
 
@@ -976,7 +981,7 @@ int smg_coarse_solve(smg_t h, const double* ru, const double* rp, double* zu, do
   int rc = check_level(h, 0);
   if (rc) return rc;
   if (!ru || !rp || !zu || !zp) return fail(SMG_EINVAL, "null vector");
-  launch_coarse_solve<double>(h->lv[0].N, h->nc, h->cinv, ru, rp, zu, zp, nullptr, (hipStream_t)sv);
+  launch_coarse_solve<double>(h->lv[0].N, h->dom, h->nc, h->cinv, ru, rp, zu, zp, nullptr, (hipStream_t)sv);
   return launch_status("smg_coarse_solve");
 }
 
@@ -992,7 +997,7 @@ int smg_project_dual(smg_t h, int level, double* v, smg_stream_t sv) {
   int rc = check_level(h, level);
   if (rc) return rc;
   if (!v) return fail(SMG_EINVAL, "null vector");
-  launch_project_dual(h->lv[level].N, v, h->red, (hipStream_t)sv);
+  launch_project_dual(h->lv[level].N, h->dom, v, h->red, (hipStream_t)sv);
   return launch_status("smg_project_dual");
 }
 
@@ -1053,10 +1058,10 @@ int smg_get_damping(smg_t h, int level, double* tau, double* sigma) {
 static void implicit_rhs(smg_hier* H, const double* f_nodal, const double* g_nodal, const double* u,
                          hipStream_t s) {
   Level& T = H->lv[H->L];
-  if (f_nodal) launch_mass_u(T.N, 2, f_nodal, T.t.u, s);
+  if (f_nodal) launch_mass_u(T.N, H->dom, 2, f_nodal, T.t.u, s);
   else launch_fill(T.t.u, T.n_u, 0.0, s);
-  launch_mass_u_acc(T.N, 0, u, H->beta, T.t.u, s);
-  if (g_nodal) launch_mass_p(T.N, g_nodal, T.t.p, s);
+  launch_mass_u_acc(T.N, H->dom, 0, u, H->beta, T.t.u, s);
+  if (g_nodal) launch_mass_p(T.N, H->dom, g_nodal, T.t.p, s);
   else launch_fill(T.t.p, T.n_p, 0.0, s);
 }
 
@@ -1084,7 +1089,7 @@ int smg_dot(smg_t h, int level, int which, const double* a, const double* b, dou
   if (rc) return rc;
   if (!a || !b || !out) return fail(SMG_EINVAL, "null vector");
   if (which != 0 && which != 1) return fail(SMG_EINVAL, "which must be 0 or 1");
-  launch_dot(h->lv[level].N, which, a, b, h->red, out, (hipStream_t)sv);
+  launch_dot(h->lv[level].N, h->dom, which, a, b, h->red, out, (hipStream_t)sv);
   return launch_status("smg_dot");
 }
 

@@ -130,13 +130,4 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-// relative P1 weights (m_i / h^2): 1 inside, 1/2 on edges, 1/3 at (0,0) and
-// (1,1), 1/6 at (1,0) and (0,1)
-__device__ __forceinline__ double p1_w(int N, int i, int j) {
-  const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
-  if (!bi && !bj) return 1.0;
-  if (bi != bj) return 0.5;
-  return (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
-}
-
 }  // namespace smg

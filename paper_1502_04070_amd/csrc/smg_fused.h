@@ -74,11 +74,11 @@ template <class T>
 int coarse_cycle_allow_lds(size_t bytes);
 
 // p -= mean from partials (sum w p, sum w) pairs of np tiles
-void launch_project_partials(const double* mpart, int np, int N, double* p, const int* done,
+void launch_project_partials(const double* mpart, int np, int N, int dom, double* p, const int* done,
                              hipStream_t s);
 // the same, then the convergence test of the solve loop from the np residual
 // partials (done by the last workgroup to finish)
-void launch_project_check(const double* mpart, const double* rpart, int np, int N, double* p,
+void launch_project_check(const double* mpart, const double* rpart, int np, int N, int dom, double* p,
                           SolveState* st, double* hist, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -98,7 +98,7 @@ void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s)
 struct PCJob {
   const double* mpart;
   const double* rpart;
-  int np, N;
+  int np, N, dom;
   double* p;
   SolveState* st;
   double* hist;

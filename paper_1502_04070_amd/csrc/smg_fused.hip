@@ -97,7 +97,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   const int ntx = (N + TX) / TX;
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
-  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
 
   // Every global input the workgroup needs is requested before the first
   // wait: the done flag, this thread's stage-1 right-hand side and Shat^-1
@@ -116,7 +116,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) f1[2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
   }
-  const bool inp1 = act1 && i1 >= 0 && i1 <= N && j1 >= 0 && j1 <= N;
+  const bool inp1 = act1 && dom_p(N, J.L.dom, i1, j1);
   f1[8] = inp1 ? J.fp[(size_t)j1 * NP + i1] : T(0);
   if (inp1) s1 = J.L.sinv[(size_t)j1 * NP + i1];
   T s2 = T(0);
@@ -144,7 +144,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
           for (int dA = 0; dA < 3; ++dA) {
             const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
+            z[dB][dA] = dom_u(Nc, J.L.dom, A, B)
                             ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
           }
         auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
@@ -173,7 +173,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         const int li = e % XPW, lj = e / XPW;
         const int i = i0 - 2 + li, j = j0 - 2 + lj;
         T v = T(0);
-        if (i >= 0 && i <= N && j >= 0 && j <= N) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
+        if (dom_p(N, J.L.dom, i, j)) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
         sxp[e] = v;
       }
     } else {
@@ -188,7 +188,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
       for (int e = tid; e < XPW * XPH; e += NT) {
         const int li = e % XPW, lj = e / XPW;
         const int i = i0 - 2 + li, j = j0 - 2 + lj;
-        sxp[e] = (i >= 0 && i <= N && j >= 0 && j <= N) ? J.xp[(size_t)j * NP + i] : T(0);
+        sxp[e] = dom_p(N, J.L.dom, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
       }
     }
     __syncthreads();
@@ -391,8 +391,8 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
   const T tau = J.tau;
-  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
-  auto inside = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
+  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
+  auto inside = [&](int i, int j) { return dom_p(N, J.L.dom, i, j); };
 
   // ---- stage 0: F and Shat^-1 on the tile + 3, the iterate on the tile + 4
   const int dn = J.done ? *J.done : 0;
@@ -426,7 +426,7 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
           for (int dA = 0; dA < 3; ++dA) {
             const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc)
+            z[dB][dA] = dom_u(Nc, J.L.dom, A, B)
                             ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
           }
         auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
@@ -647,7 +647,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   const int ntx = (Nc + TC) / TC;
   const int I0 = (tile % ntx) * TC, J0 = (tile / ntx) * TC;
   const int tid = threadIdx.x;
-  auto interior = [&](int a, int b) { return a > 0 && a < 2 * N && b > 0 && b < 2 * N; };
+  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
   // the done flag and this thread's stage-1 right-hand sides (at most two
   // squares per thread) are requested together with the iterate window
   static_assert(NC1 * NC1 <= 2 * NT, "at most two stage-1 squares per thread");
@@ -665,7 +665,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) f1[it][2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
     }
-    const bool inp = act && i >= 0 && i <= N && j >= 0 && j <= N;
+    const bool inp = act && dom_p(N, J.L.dom, i, j);
     f1[it][8] = inp ? J.fp[(size_t)j * NP + i] : T(0);
   }
   for (int e = tid; e < XW * XW; e += NT) {
@@ -679,7 +679,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   for (int e = tid; e < XPW * XPW; e += NT) {
     const int li = e % XPW, lj = e / XPW;
     const int i = 2 * I0 - 3 + li, j = 2 * J0 - 3 + lj;
-    sxp[e] = (i >= 0 && i <= N && j >= 0 && j <= N) ? J.xp[(size_t)j * NP + i] : T(0);
+    sxp[e] = dom_p(N, J.L.dom, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
   }
   __syncthreads();
   if (dn) return;   // uniform across the workgroup
@@ -700,7 +700,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) sr[c][2 * cj + DB][2 * ci + DA] = in ? f1[it][2 * cls + c] - y[2 * cls + c] : T(0);
     }
-    const bool inp = i >= 0 && i <= N && j >= 0 && j <= N;
+    const bool inp = dom_p(N, J.L.dom, i, j);
     srp[cj * RPW + ci] = inp ? f1[it][8] - y[8] : T(0);
   }
   __syncthreads();
@@ -712,7 +712,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     const int CA = cls & 1, CB = cls >> 1;
     const int A = 2 * I + CA, B = 2 * Jc + CB;
     if (A <= 2 * Nc && B <= 2 * Nc) {
-      const bool in = A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc;
+      const bool in = dom_u(Nc, J.L.dom, A, B);
       const int la = 4 * tx + 2 * CA + 4, lb = 4 * ty + 2 * CB + 4;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -732,7 +732,9 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     if (cls == 3) {
       auto Rp = [&](int di, int dj) -> T { return srp[(2 * ty + 2 + dj) * RPW + (2 * tx + 2 + di)]; };
       J.cp[(size_t)Jc * NPc + I] =
-          Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1));
+          dom_p(Nc, J.L.dom, I, Jc)
+              ? Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1))
+              : T(0);
     }
   }
 }
@@ -839,7 +841,7 @@ template int coarse_cycle_allow_lds<float>(size_t);
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_project_partials(const double* __restrict__ mpart, int np, int N,
-                                                          double* p, const int* done) {
+                                                          int dom, double* p, const int* done) {
   if (done && *done) return;
   __shared__ double red[4];
   __shared__ double sh_mean;
@@ -857,14 +859,14 @@ __global__ __launch_bounds__(256) void k_project_partials(const double* __restri
   const double m = sh_mean;
   for (int k = 0; k < 4; ++k) {
     const int e = blockIdx.x * 1024 + k * 256 + threadIdx.x;
-    if (e < n) p[e] -= m;
+    if (e < n && dom_p(N, dom, e % (N + 1), e / (N + 1))) p[e] -= m;
   }
 }
 
-void launch_project_partials(const double* mpart, int np, int N, double* p, const int* done,
+void launch_project_partials(const double* mpart, int np, int N, int dom, double* p, const int* done,
                              hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_project_partials<<<(n + 1023) / 1024, 256, 0, s>>>(mpart, np, N, p, done);
+  k_project_partials<<<(n + 1023) / 1024, 256, 0, s>>>(mpart, np, N, dom, p, done);
 }
 
 // Mean projection by every workgroup, then the convergence test by the last
@@ -873,8 +875,8 @@ void launch_project_partials(const double* mpart, int np, int N, double* p, cons
 // order, so the test is deterministic.
 __device__ __forceinline__ void project_check_body(const double* __restrict__ mpart,
                                                    const double* __restrict__ rpart, int np, int N,
-                                                   double* p, SolveState* st, double* hist, int blk,
-                                                   int nblk) {
+                                                   int dom, double* p, SolveState* st, double* hist,
+                                                   int blk, int nblk) {
   __shared__ double red[4];
   __shared__ double sh_mean;
   __shared__ int sh_last;
@@ -892,7 +894,7 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   const double m = sh_mean;
   for (int k = 0; k < 4; ++k) {
     const int e = blk * 1024 + k * 256 + threadIdx.x;
-    if (e < n) p[e] -= m;
+    if (e < n && dom_p(N, dom, e % (N + 1), e / (N + 1))) p[e] -= m;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -921,16 +923,16 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
 
 __global__ __launch_bounds__(256) void k_project_check(const double* __restrict__ mpart,
                                                        const double* __restrict__ rpart, int np, int N,
-                                                       double* p, SolveState* st, double* hist) {
+                                                       int dom, double* p, SolveState* st, double* hist) {
   if (st->done) return;
-  project_check_body(mpart, rpart, np, N, p, st, hist, blockIdx.x, gridDim.x);
+  project_check_body(mpart, rpart, np, N, dom, p, st, hist, blockIdx.x, gridDim.x);
 }
 
 __host__ __device__ int pc_blocks(int N) { return ((N + 1) * (N + 1) + 1023) / 1024; }
 
-void launch_project_check(const double* mpart, const double* rpart, int np, int N, double* p,
+void launch_project_check(const double* mpart, const double* rpart, int np, int N, int dom, double* p,
                           SolveState* st, double* hist, hipStream_t s) {
-  k_project_check<<<pc_blocks(N), 256, 0, s>>>(mpart, rpart, np, N, p, st, hist);
+  k_project_check<<<pc_blocks(N), 256, 0, s>>>(mpart, rpart, np, N, dom, p, st, hist);
 }
 
 template <bool PACK>
@@ -938,7 +940,7 @@ __global__ __launch_bounds__(256) void k_pc_b(const JobArg<PCJob> A) {
   int tile;
   const PCJob J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.st->done) return;
-  project_check_body(J.mpart, J.rpart, J.np, J.N, J.p, J.st, J.hist, tile, pc_blocks(J.N));
+  project_check_body(J.mpart, J.rpart, J.np, J.N, J.dom, J.p, J.st, J.hist, tile, pc_blocks(J.N));
 }
 
 void launch_pc_b(const JobArg<PCJob>& A, int nb, hipStream_t s) {

@@ -42,11 +42,40 @@ __device__ __forceinline__ J block_job(const JobArg<J>& A, int b, int& tile) {
   }
 }
 
+// Domains on the grid of N x N squares (lattice point (a, b) at
+// (a / 2N, b / 2N), vertex (i, j) at (i / N, j / N)):
+//   0: the unit square;
+//   1: the L-shape, the unit square without [1/2, 1]^2 (N even).
+// dom_u: the lattice point carries velocity unknowns (inside, off the boundary);
+// dom_p: the vertex belongs to the closed domain (pressure node);
+// dom_sq: the square belongs to the domain.
+enum { SMG_DOM_SQUARE = 0, SMG_DOM_LSHAPE = 1 };
+
+__host__ __device__ inline bool dom_u(int N, int dom, int a, int b) {
+  return a > 0 && a < 2 * N && b > 0 && b < 2 * N && !(dom == SMG_DOM_LSHAPE && a >= N && b >= N);
+}
+__host__ __device__ inline bool dom_p(int N, int dom, int i, int j) {
+  return i >= 0 && i <= N && j >= 0 && j <= N && !(dom == SMG_DOM_LSHAPE && 2 * i > N && 2 * j > N);
+}
+__host__ __device__ inline bool dom_sq(int N, int dom, int si, int sj) {
+  return si >= 0 && si < N && sj >= 0 && sj < N && !(dom == SMG_DOM_LSHAPE && 2 * si >= N && 2 * sj >= N);
+}
+// int phi_i / h^2 of the P1 basis function of vertex (i, j): (h^2 / 6) times
+// the number of triangles of the domain around it (the same-diagonal grid
+// has two triangles of square (i-1, j-1) and of square (i, j) at the vertex,
+// one of square (i, j-1) and one of square (i-1, j))
+__host__ __device__ inline double p1_count_w(int N, int dom, int i, int j) {
+  const int c = 2 * dom_sq(N, dom, i - 1, j - 1) + dom_sq(N, dom, i, j - 1) + dom_sq(N, dom, i - 1, j) +
+                2 * dom_sq(N, dom, i, j);
+  return c / 6.0;
+}
+
 // Per-level constants of the operator (Section 2 matrices, Section 6
 // preconditioner), in the arithmetic type T of the kernels.
 template <class T>
 struct LevelCoef {
   int N;             // cells per side
+  int dom;           // domain (SMG_DOM_*)
   T acoef[4][5];     // A = K + beta h^2 M, grouped lattice taps per node class
   T adinv[4];        // 1 / Ahat per node class (V, H, E, D)
   T h;               // 1 / N (scales B and B^T)
@@ -101,6 +130,7 @@ int stencil_tiles_shape(int N, int tx, int ty);
 template <class T>
 struct ProJob {
   int Nc;
+  int dom;
   const T* zu;
   const T* zp;
   T* u;
@@ -123,38 +153,38 @@ void launch_ew_b(const JobArg<EwJob>& A, int nb, int mode, hipStream_t s);
 
 // r_c = P^T r_f (velocity P2, pressure P1); also zero (xcu, xcp) if not NULL.
 template <class T>
-void launch_restrict(int Nc, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
+void launch_restrict(int Nc, int dom, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
                      const int* done, hipStream_t s);
 // (u, p) += P (zu, zp)
 template <class T>
-void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
+void launch_prolong_add(int Nc, int dom, const T* zu, const T* zp, T* u, T* p, const int* done,
                         hipStream_t s);
 // z = Cinv * [r; 0] on the coarsest grid (FP64 inverse, any T in / out)
 template <class T>
-void launch_coarse_solve(int N0, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
+void launch_coarse_solve(int N0, int dom, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
                          T* zp, const int* done, hipStream_t s);
 
 // p <- p - (m . p) / sum(m); uses `partials` (>= mean_blocks(N) doubles x 2)
 int mean_blocks(int N);
-void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s);
+void launch_project_mean(int N, int dom, double* p, double* partials, const int* done, hipStream_t s);
 // v <- v - m (sum_i v_i) / (sum_i m_i): the transpose of the mean projection
-void launch_project_dual(int N, double* p, double* partials, hipStream_t s);
+void launch_project_dual(int N, int dom, double* p, double* partials, hipStream_t s);
 
 // Shat^-1 at setup
 template <class T>
-void launch_shat_inv(int N, const T* adinv_host4, T* sinv, hipStream_t s);
+void launch_shat_inv(int N, int dom, const T* adinv_host4, T* sinv, hipStream_t s);
 
 // load vectors / masses
 // mode 0: interior rows from interior values; 1: all rows from interior values;
 // 2: interior rows from all values (load vectors of nodal data)
-void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s);
+void launch_mass_u(int N, int dom, int mode, const double* u, double* y, hipStream_t s);
 // y += scale * (M u) on the rows of `mode` (same modes as launch_mass_u)
-void launch_mass_u_acc(int N, int mode, const double* u, double scale, double* y, hipStream_t s);
-void launch_mass_p(int N, const double* g, double* gp, hipStream_t s);
+void launch_mass_u_acc(int N, int dom, int mode, const double* u, double scale, double* y, hipStream_t s);
+void launch_mass_p(int N, int dom, const double* g, double* gp, hipStream_t s);
 
 // deterministic dots: which = 0 velocity interior lattice points, 1 pressure
 int dot_blocks(int N, int which);
-void launch_dot(int N, int which, const double* a, const double* b, double* partials,
+void launch_dot(int N, int dom, int which, const double* a, const double* b, double* partials,
                 double* out, hipStream_t s);
 // out[0] = sum of np partials (fixed order)
 void launch_reduce(const double* partials, int np, double* out, hipStream_t s);

@@ -118,7 +118,7 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
   const int N = J.L.N, M = 2 * N + 1;
   const int a = 2 * i + DA, b = 2 * j + DB;
   if (a > 2 * N || b > 2 * N) return;
-  const bool interior = (a > 0) && (a < 2 * N) && (b > 0) && (b < 2 * N);
+  const bool interior = dom_u(N, J.L.dom, a, b);
   const int la = 2 * tx + 2 + DA, lb = 2 * ty + 2 + DB;
   const bool hu = FL::on(F_IN_U, J.in_u);
   const bool hp = FL::on(F_IN_P, J.in_p);
@@ -162,7 +162,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
     for (int e = tid; e < WX * WY; e += NT) {
       const int la = e % WX, lb = e / WX;
       const int a = 2 * i0 - 2 + la, b = 2 * j0 - 2 + lb;
-      const bool in = (a > 0) && (a < 2 * N) && (b > 0) && (b < 2 * N);
+      const bool in = dom_u(N, J.L.dom, a, b);
       const size_t g = (size_t)b * M + a;
       su[0][lb][la] = in ? J.in_u[g] : T(0);
       su[1][lb][la] = in ? J.in_u[(size_t)M * M + g] : T(0);
@@ -173,7 +173,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       const int li = e % PX, lj = e / PX;
       const int i = i0 - 1 + li, j = j0 - 1 + lj;
       T v = T(0);
-      if (i >= 0 && i <= N && j >= 0 && j <= N) {
+      if (dom_p(N, J.L.dom, i, j)) {
         v = J.in_p[(size_t)j * NP + i];
         if (FL::on(F_PSUB, J.in_p_sub)) v -= J.in_p_sub[(size_t)j * NP + i];
       }
@@ -197,11 +197,13 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       auto U1 = [&](int da, int db) -> T { return su[1][lb + db][la + da]; };
       const T y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
       const size_t g = (size_t)j * NP + i;
-      const T r = (FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y;
+      // vertices outside the domain carry no pressure unknown: zero row
+      const bool pin = dom_p(N, J.L.dom, i, j);
+      const T r = pin ? (FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y : T(0);
       if (FL::on(F_PARTIAL, J.partial)) nrm += (double)r * (double)r;
       if (FL::on(F_OUT_P, J.out_p)) {
         const T d = FL::on_int(F_DIAG_P, J.diag_p) ? J.L.sinv[g] : T(1);
-        J.out_p[g] = (FL::on(F_BASE_P, J.base_p) ? J.base_p[g] : T(0)) + J.w_p * d * r;
+        J.out_p[g] = pin ? (FL::on(F_BASE_P, J.base_p) ? J.base_p[g] : T(0)) + J.w_p * d * r : T(0);
       }
     }
   }
@@ -213,8 +215,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
     // pressure mean pieces of in_p over the owned vertices
     double w = 0.0, wp = 0.0;
     if (i <= N && j <= N) {
-      const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
-      w = (!bi && !bj) ? 1.0 : (bi != bj) ? 0.5 : (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
+      w = p1_count_w(N, J.L.dom, i, j);
       wp = w * (double)sp[ty + 1][tx + 1];
     }
     __syncthreads();
@@ -379,18 +380,18 @@ template void launch_stencil_b<float>(const JobArg<StencilJob<float>>&, int, int
 // ---------------------------------------------------------------------------
 
 template <int CLS, class T>
-__device__ __forceinline__ void restrict_node(int Nc, int I, int J, const T* rfu, T* rcu, T* xcu) {
+__device__ __forceinline__ void restrict_node(int Nc, int dom, int I, int J, const T* rfu, T* rcu, T* xcu) {
   constexpr int CA = CLS & 1, CB = CLS >> 1;
   const int A = 2 * I + CA, B = 2 * J + CB;
   if (A > 2 * Nc || B > 2 * Nc) return;
   const int Mc = 2 * Nc + 1, Mf = 4 * Nc + 1;
-  const bool interior = A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc;
+  const bool interior = dom_u(Nc, dom, A, B);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const T* rf = rfu + (size_t)c * Mf * Mf;
     auto R = [&](int fa, int fb) -> T {
       const int a = 2 * A + fa, b = 2 * B + fb;
-      return (a > 0 && a < Mf - 1 && b > 0 && b < Mf - 1) ? rf[(size_t)b * Mf + a] : T(0);
+      return dom_u(2 * Nc, dom, a, b) ? rf[(size_t)b * Mf + a] : T(0);
     };
     const T v = interior ? res_row<CLS, T>(R) : T(0);
     const size_t g = (size_t)c * Mc * Mc + (size_t)B * Mc + A;
@@ -400,37 +401,37 @@ __device__ __forceinline__ void restrict_node(int Nc, int I, int J, const T* rfu
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_restrict(int Nc, const T* __restrict__ rfu,
+__global__ __launch_bounds__(256) void k_restrict(int Nc, int dom, const T* __restrict__ rfu,
                                                   const T* __restrict__ rfp, T* rcu, T* rcp,
                                                   T* xcu, T* xcp, const int* done) {
   if (done && *done) return;
   const int I = blockIdx.x * 16 + (threadIdx.x & 15);
   const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
   if (I > Nc || J > Nc) return;
-  restrict_node<0, T>(Nc, I, J, rfu, rcu, xcu);
-  restrict_node<1, T>(Nc, I, J, rfu, rcu, xcu);
-  restrict_node<2, T>(Nc, I, J, rfu, rcu, xcu);
-  restrict_node<3, T>(Nc, I, J, rfu, rcu, xcu);
+  restrict_node<0, T>(Nc, dom, I, J, rfu, rcu, xcu);
+  restrict_node<1, T>(Nc, dom, I, J, rfu, rcu, xcu);
+  restrict_node<2, T>(Nc, dom, I, J, rfu, rcu, xcu);
+  restrict_node<3, T>(Nc, dom, I, J, rfu, rcu, xcu);
   const int Nf = 2 * Nc, NPf = Nf + 1;
   auto Rp = [&](int i, int j) -> T {
-    return (i >= 0 && i <= Nf && j >= 0 && j <= Nf) ? rfp[(size_t)j * NPf + i] : T(0);
+    return dom_p(Nf, dom, i, j) ? rfp[(size_t)j * NPf + i] : T(0);
   };
   const int fi = 2 * I, fj = 2 * J;
   const T v = Rp(fi, fj) + T(0.5) * (Rp(fi + 1, fj) + Rp(fi - 1, fj) + Rp(fi, fj + 1) +
                                      Rp(fi, fj - 1) + Rp(fi + 1, fj + 1) + Rp(fi - 1, fj - 1));
-  rcp[(size_t)J * (Nc + 1) + I] = v;
+  rcp[(size_t)J * (Nc + 1) + I] = dom_p(Nc, dom, I, J) ? v : T(0);
   if (xcp) xcp[(size_t)J * (Nc + 1) + I] = T(0);
 }
 
 template <class T>
-void launch_restrict(int Nc, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
+void launch_restrict(int Nc, int dom, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
                      const int* done, hipStream_t s) {
   dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
-  k_restrict<T><<<grid, 256, 0, s>>>(Nc, rfu, rfp, rcu, rcp, xcu, xcp, done);
+  k_restrict<T><<<grid, 256, 0, s>>>(Nc, dom, rfu, rfp, rcu, rcp, xcu, xcp, done);
 }
-template void launch_restrict<double>(int, const double*, const double*, double*, double*,
+template void launch_restrict<double>(int, int, const double*, const double*, double*, double*,
                                       double*, double*, const int*, hipStream_t);
-template void launch_restrict<float>(int, const float*, const float*, float*, float*, float*,
+template void launch_restrict<float>(int, int, const float*, const float*, float*, float*, float*,
                                      float*, const int*, hipStream_t);
 
 template <int RA, int RB, class T, class FZ>
@@ -454,15 +455,15 @@ __device__ __forceinline__ T pro_weights(FZ Z) {
 }
 
 template <int RA, int RB, class T, class FZ>
-__device__ __forceinline__ void pro_point(int Nf, int I, int J, FZ Z, T* uf) {
+__device__ __forceinline__ void pro_point(int Nf, int dom, int I, int J, FZ Z, T* uf) {
   const int a = 4 * I + RA, b = 4 * J + RB;
-  if (a <= 0 || a >= 2 * Nf || b <= 0 || b >= 2 * Nf) return;
+  if (!dom_u(Nf, dom, a, b)) return;
   uf[(size_t)b * (2 * Nf + 1) + a] += pro_weights<RA, RB, T>(Z);
 }
 
 template <class T>
-__device__ __forceinline__ void prolong_body(int Nc, const T* __restrict__ zu, const T* __restrict__ zp,
-                                             T* u, T* p, int bx, int by) {
+__device__ __forceinline__ void prolong_body(int Nc, int dom, const T* __restrict__ zu,
+                                             const T* __restrict__ zp, T* u, T* p, int bx, int by) {
   const int I = bx * 16 + (threadIdx.x & 15);
   const int J = by * 16 + (threadIdx.x >> 4);
   if (I > Nc || J > Nc) return;
@@ -473,33 +474,35 @@ __device__ __forceinline__ void prolong_body(int Nc, const T* __restrict__ zu, c
     T* uf = u + (size_t)c * Mf * Mf;
     auto Z = [&](int dA, int dB) -> T {
       const int A = 2 * I + dA, B = 2 * J + dB;
-      return (A > 0 && A < 2 * Nc && B > 0 && B < 2 * Nc) ? z[(size_t)B * Mc + A] : T(0);
+      return dom_u(Nc, dom, A, B) ? z[(size_t)B * Mc + A] : T(0);
     };
-    pro_point<0, 0, T>(Nf, I, J, Z, uf); pro_point<1, 0, T>(Nf, I, J, Z, uf);
-    pro_point<2, 0, T>(Nf, I, J, Z, uf); pro_point<3, 0, T>(Nf, I, J, Z, uf);
-    pro_point<0, 1, T>(Nf, I, J, Z, uf); pro_point<1, 1, T>(Nf, I, J, Z, uf);
-    pro_point<2, 1, T>(Nf, I, J, Z, uf); pro_point<3, 1, T>(Nf, I, J, Z, uf);
-    pro_point<0, 2, T>(Nf, I, J, Z, uf); pro_point<1, 2, T>(Nf, I, J, Z, uf);
-    pro_point<2, 2, T>(Nf, I, J, Z, uf); pro_point<3, 2, T>(Nf, I, J, Z, uf);
-    pro_point<0, 3, T>(Nf, I, J, Z, uf); pro_point<1, 3, T>(Nf, I, J, Z, uf);
-    pro_point<2, 3, T>(Nf, I, J, Z, uf); pro_point<3, 3, T>(Nf, I, J, Z, uf);
+    pro_point<0, 0, T>(Nf, dom, I, J, Z, uf); pro_point<1, 0, T>(Nf, dom, I, J, Z, uf);
+    pro_point<2, 0, T>(Nf, dom, I, J, Z, uf); pro_point<3, 0, T>(Nf, dom, I, J, Z, uf);
+    pro_point<0, 1, T>(Nf, dom, I, J, Z, uf); pro_point<1, 1, T>(Nf, dom, I, J, Z, uf);
+    pro_point<2, 1, T>(Nf, dom, I, J, Z, uf); pro_point<3, 1, T>(Nf, dom, I, J, Z, uf);
+    pro_point<0, 2, T>(Nf, dom, I, J, Z, uf); pro_point<1, 2, T>(Nf, dom, I, J, Z, uf);
+    pro_point<2, 2, T>(Nf, dom, I, J, Z, uf); pro_point<3, 2, T>(Nf, dom, I, J, Z, uf);
+    pro_point<0, 3, T>(Nf, dom, I, J, Z, uf); pro_point<1, 3, T>(Nf, dom, I, J, Z, uf);
+    pro_point<2, 3, T>(Nf, dom, I, J, Z, uf); pro_point<3, 3, T>(Nf, dom, I, J, Z, uf);
   }
   // P1: copy at coarse vertices, mean of the two ends at edge midpoints
   const int NPc = Nc + 1, NPf = Nf + 1;
   auto Zp = [&](int i, int j) -> T { return zp[(size_t)j * NPc + i]; };
   const int fi = 2 * I, fj = 2 * J;
-  p[(size_t)fj * NPf + fi] += Zp(I, J);
-  if (I < Nc) p[(size_t)fj * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J));
-  if (J < Nc) p[(size_t)(fj + 1) * NPf + fi] += T(0.5) * (Zp(I, J) + Zp(I, J + 1));
-  if (I < Nc && J < Nc) p[(size_t)(fj + 1) * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J + 1));
+  // fine vertices of the domain only (their coarse parents belong to it too)
+  if (dom_p(Nf, dom, fi, fj)) p[(size_t)fj * NPf + fi] += Zp(I, J);
+  if (I < Nc && dom_p(Nf, dom, fi + 1, fj)) p[(size_t)fj * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J));
+  if (J < Nc && dom_p(Nf, dom, fi, fj + 1)) p[(size_t)(fj + 1) * NPf + fi] += T(0.5) * (Zp(I, J) + Zp(I, J + 1));
+  if (I < Nc && J < Nc && dom_p(Nf, dom, fi + 1, fj + 1))
+    p[(size_t)(fj + 1) * NPf + fi + 1] += T(0.5) * (Zp(I, J) + Zp(I + 1, J + 1));
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_prolong_add(int Nc, const T* __restrict__ zu,
+__global__ __launch_bounds__(256) void k_prolong_add(int Nc, int dom, const T* __restrict__ zu,
                                                      const T* __restrict__ zp, T* u, T* p,
                                                      const int* done) {
   if (done && *done) return;
-  prolong_body<T>(Nc, zu, zp, u, p, blockIdx.x, blockIdx.y);
+  prolong_body<T>(Nc, dom, zu, zp, u, p, blockIdx.x, blockIdx.y);
 }
 
 int prolong_tiles(int Nc) { return ((Nc + 16) / 16) * ((Nc + 16) / 16); }
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(256) void k_prolong_b(const JobArg<ProJob<T>> A) {
   const ProJob<T> J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.done && *J.done) return;
   const int ntx = (J.Nc + 16) / 16;
-  prolong_body<T>(J.Nc, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
+  prolong_body<T>(J.Nc, J.dom, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
 }
 
 template <class T>
@@ -522,14 +525,14 @@ template void launch_prolong_b<double>(const JobArg<ProJob<double>>&, int, hipSt
 template void launch_prolong_b<float>(const JobArg<ProJob<float>>&, int, hipStream_t);
 
 template <class T>
-void launch_prolong_add(int Nc, const T* zu, const T* zp, T* u, T* p, const int* done,
+void launch_prolong_add(int Nc, int dom, const T* zu, const T* zp, T* u, T* p, const int* done,
                         hipStream_t s) {
   dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
-  k_prolong_add<T><<<grid, 256, 0, s>>>(Nc, zu, zp, u, p, done);
+  k_prolong_add<T><<<grid, 256, 0, s>>>(Nc, dom, zu, zp, u, p, done);
 }
-template void launch_prolong_add<double>(int, const double*, const double*, double*, double*,
+template void launch_prolong_add<double>(int, int, const double*, const double*, double*, double*,
                                          const int*, hipStream_t);
-template void launch_prolong_add<float>(int, const float*, const float*, float*, float*,
+template void launch_prolong_add<float>(int, int, const float*, const float*, float*, float*,
                                         const int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -539,7 +542,7 @@ template void launch_prolong_add<float>(int, const float*, const float*, float*,
 // ---------------------------------------------------------------------------
 
 template <class T>
-__global__ __launch_bounds__(256) void k_coarse_solve(int N0, int nc, const double* __restrict__ cinv,
+__global__ __launch_bounds__(256) void k_coarse_solve(int N0, int dom, int nc, const double* __restrict__ cinv,
                                                       const T* ru, const T* rp, T* zu, T* zp,
                                                       const int* done) {
   if (done && *done) return;
@@ -569,33 +572,29 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N0, int nc, const doub
     const int c = k / (M0 * M0), q = k % (M0 * M0);
     const int a = q % M0, b = q / M0;
     T v = T(0);
-    if (a > 0 && a < 2 * N0 && b > 0 && b < 2 * N0) v = (T)sz[c * nu + (b - 1) * ni + (a - 1)];
+    if (dom_u(N0, dom, a, b)) v = (T)sz[c * nu + (b - 1) * ni + (a - 1)];
     zu[k] = v;
   }
-  for (int k = threadIdx.x; k < NP * NP; k += blockDim.x) zp[k] = (T)sz[2 * nu + k];
+  for (int k = threadIdx.x; k < NP * NP; k += blockDim.x)
+    zp[k] = dom_p(N0, dom, k % NP, k / NP) ? (T)sz[2 * nu + k] : T(0);
 }
 
 template <class T>
-void launch_coarse_solve(int N0, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
+void launch_coarse_solve(int N0, int dom, int nc, const double* cinv, const T* ru, const T* rp, T* zu,
                          T* zp, const int* done, hipStream_t s) {
-  k_coarse_solve<T><<<1, 256, 2 * nc * sizeof(double), s>>>(N0, nc, cinv, ru, rp, zu, zp, done);
+  k_coarse_solve<T><<<1, 256, 2 * nc * sizeof(double), s>>>(N0, dom, nc, cinv, ru, rp, zu, zp, done);
 }
-template void launch_coarse_solve<double>(int, int, const double*, const double*, const double*,
+template void launch_coarse_solve<double>(int, int, int, const double*, const double*, const double*,
                                           double*, double*, const int*, hipStream_t);
-template void launch_coarse_solve<float>(int, int, const double*, const float*, const float*,
+template void launch_coarse_solve<float>(int, int, int, const double*, const float*, const float*,
                                          float*, float*, const int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// pressure mean: p <- p - (m . p) / sum m, m_i = int phi_i (relative weights:
-// 1 inside, 1/2 on edges, 1/3 at (0,0) and (1,1), 1/6 at (1,0) and (0,1))
+// pressure mean: p <- p - (m . p) / sum m, m_i = int phi_i (relative weights
+// from the triangles of the domain around each vertex: on the unit square 1
+// inside, 1/2 on edges, 1/3 at (0,0) and (1,1), 1/6 at (1,0) and (0,1)).
+// Vertices outside the domain keep their (zero) value.
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double p1_weight(int N, int i, int j) {
-  const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N);
-  if (!bi && !bj) return 1.0;
-  if (bi != bj) return 0.5;
-  return (i == j) ? (1.0 / 3.0) : (1.0 / 6.0);
-}
 
 constexpr int MEAN_PER_THREAD = 4;
 int mean_blocks(int N) {
@@ -605,7 +604,7 @@ int mean_blocks(int N) {
 
 // mode 0: p <- p - (sum w p / sum w)          (mean projection)
 // mode 1: p <- p - w (sum p / sum w)          (its transpose, Pi^T)
-__global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __restrict__ p,
+__global__ __launch_bounds__(256) void k_mean_partial(int N, int dom, const double* __restrict__ p,
                                                       double* partials, const int* done, int mode) {
   if (done && *done) return;
   __shared__ double red[4];
@@ -614,8 +613,8 @@ __global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __res
   for (int k = 0; k < MEAN_PER_THREAD; ++k) {
     const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
     if (e < n) {
-      const double w = p1_weight(N, e % (N + 1), e / (N + 1));
-      s1 += (mode == 0 ? w : 1.0) * p[e];
+      const double w = p1_count_w(N, dom, e % (N + 1), e / (N + 1));
+      s1 += (mode == 0 ? w : (w > 0 ? 1.0 : 0.0)) * p[e];
       s2 += w;
     }
   }
@@ -628,8 +627,9 @@ __global__ __launch_bounds__(256) void k_mean_partial(int N, const double* __res
   }
 }
 
-__global__ __launch_bounds__(256) void k_mean_apply(int N, double* p, const double* __restrict__ partials,
-                                                    int nparts, const int* done, int mode) {
+__global__ __launch_bounds__(256) void k_mean_apply(int N, int dom, double* p,
+                                                    const double* __restrict__ partials, int nparts,
+                                                    const int* done, int mode) {
   if (done && *done) return;
   __shared__ double red[4];
   __shared__ double mean;
@@ -646,20 +646,23 @@ __global__ __launch_bounds__(256) void k_mean_apply(int N, double* p, const doub
   const int n = (N + 1) * (N + 1);
   for (int k = 0; k < MEAN_PER_THREAD; ++k) {
     const int e = blockIdx.x * 256 * MEAN_PER_THREAD + k * 256 + threadIdx.x;
-    if (e < n) p[e] -= (mode == 0 ? 1.0 : p1_weight(N, e % (N + 1), e / (N + 1))) * mean;
+    if (e < n) {
+      const double w = p1_count_w(N, dom, e % (N + 1), e / (N + 1));
+      if (w > 0) p[e] -= (mode == 0 ? 1.0 : w) * mean;
+    }
   }
 }
 
-void launch_project_mean(int N, double* p, double* partials, const int* done, hipStream_t s) {
+void launch_project_mean(int N, int dom, double* p, double* partials, const int* done, hipStream_t s) {
   const int nb = mean_blocks(N);
-  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, done, 0);
-  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, done, 0);
+  k_mean_partial<<<nb, 256, 0, s>>>(N, dom, p, partials, done, 0);
+  k_mean_apply<<<nb, 256, 0, s>>>(N, dom, p, partials, nb, done, 0);
 }
 
-void launch_project_dual(int N, double* p, double* partials, hipStream_t s) {
+void launch_project_dual(int N, int dom, double* p, double* partials, hipStream_t s) {
   const int nb = mean_blocks(N);
-  k_mean_partial<<<nb, 256, 0, s>>>(N, p, partials, nullptr, 1);
-  k_mean_apply<<<nb, 256, 0, s>>>(N, p, partials, nb, nullptr, 1);
+  k_mean_partial<<<nb, 256, 0, s>>>(N, dom, p, partials, nullptr, 1);
+  k_mean_apply<<<nb, 256, 0, s>>>(N, dom, p, partials, nb, nullptr, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -668,41 +671,39 @@ void launch_project_dual(int N, double* p, double* partials, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 template <class T>
-__global__ __launch_bounds__(256) void k_shat_inv(int N, T ad0, T ad1, T ad2, T ad3, T* sinv) {
+__global__ __launch_bounds__(256) void k_shat_inv(int N, int dom, T ad0, T ad1, T ad2, T ad3, T* sinv) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= (N + 1) * (N + 1)) return;
   const int i = e % (N + 1), j = e / (N + 1);
   const T h = T(1) / T(N);
-  auto IN = [&](int da, int db) -> bool {
-    const int a = 2 * i + da, b = 2 * j + db;
-    return a > 0 && a < 2 * N && b > 0 && b < 2 * N;
-  };
+  auto IN = [&](int da, int db) -> bool { return dom_u(N, dom, 2 * i + da, 2 * j + db); };
   auto AD = [&](int c) -> T { return c == 0 ? ad0 : c == 1 ? ad1 : c == 2 ? ad2 : ad3; };
   const T S = h * h * SMG_SHAT_ROW(IN, AD);
-  sinv[e] = T(1) / S;
+  // a vertex outside the domain couples to no unknown: no pressure update there
+  sinv[e] = dom_p(N, dom, i, j) ? T(1) / S : T(0);
 }
 
 template <class T>
-void launch_shat_inv(int N, const T* ad, T* sinv, hipStream_t s) {
+void launch_shat_inv(int N, int dom, const T* ad, T* sinv, hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_shat_inv<T><<<(n + 255) / 256, 256, 0, s>>>(N, ad[0], ad[1], ad[2], ad[3], sinv);
+  k_shat_inv<T><<<(n + 255) / 256, 256, 0, s>>>(N, dom, ad[0], ad[1], ad[2], ad[3], sinv);
 }
-template void launch_shat_inv<double>(int, const double*, double*, hipStream_t);
-template void launch_shat_inv<float>(int, const float*, float*, hipStream_t);
+template void launch_shat_inv<double>(int, int, const double*, double*, hipStream_t);
+template void launch_shat_inv<float>(int, int, const float*, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // masses (load vectors and the adjoint): one thread per square, direct loads
 // ---------------------------------------------------------------------------
 
 template <int CLS>
-__device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int read_all,
+__device__ __forceinline__ void mass_node(int N, int dom, int i, int j, int rows_all, int read_all,
                                           const double* u, double* y, double scale, int acc) {
   using T = double;
   constexpr int DA = CLS & 1, DB = CLS >> 1;
   const int M = 2 * N + 1;
   const int a = 2 * i + DA, b = 2 * j + DB;
   if (a > 2 * N || b > 2 * N) return;
-  const bool interior = a > 0 && a < 2 * N && b > 0 && b < 2 * N;
+  const bool interior = dom_u(N, dom, a, b);
   const double h2 = 1.0 / ((double)N * (double)N);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -710,7 +711,7 @@ __device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int
     auto U = [&](int da, int db) -> T {
       const int aa = a + da, bb = b + db;
       const bool ok = read_all ? (aa >= 0 && aa <= 2 * N && bb >= 0 && bb <= 2 * N)
-                               : (aa > 0 && aa < 2 * N && bb > 0 && bb < 2 * N);
+                               : dom_u(N, dom, aa, bb);
       return ok ? uc[(size_t)bb * M + aa] : 0.0;
     };
     const double v = (interior || rows_all) ? h2 * m_row<CLS, T>(U) : 0.0;
@@ -719,37 +720,37 @@ __device__ __forceinline__ void mass_node(int N, int i, int j, int rows_all, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_mass_u(int N, int rows_all, int read_all,
+__global__ __launch_bounds__(256) void k_mass_u(int N, int dom, int rows_all, int read_all,
                                                 const double* __restrict__ u, double* y, double scale,
                                                 int acc) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= (N + 1) * (N + 1)) return;
   const int i = e % (N + 1), j = e / (N + 1);
-  mass_node<0>(N, i, j, rows_all, read_all, u, y, scale, acc);
-  mass_node<1>(N, i, j, rows_all, read_all, u, y, scale, acc);
-  mass_node<2>(N, i, j, rows_all, read_all, u, y, scale, acc);
-  mass_node<3>(N, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<0>(N, dom, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<1>(N, dom, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<2>(N, dom, i, j, rows_all, read_all, u, y, scale, acc);
+  mass_node<3>(N, dom, i, j, rows_all, read_all, u, y, scale, acc);
 }
 
-void launch_mass_u(int N, int mode, const double* u, double* y, hipStream_t s) {
+void launch_mass_u(int N, int dom, int mode, const double* u, double* y, hipStream_t s) {
   // mode 0: rows interior, read interior; 1: rows all, read interior; 2: rows interior, read all
   const int n = (N + 1) * (N + 1);
-  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, 1.0, 0);
+  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, 1.0, 0);
 }
 
-void launch_mass_u_acc(int N, int mode, const double* u, double scale, double* y, hipStream_t s) {
+void launch_mass_u_acc(int N, int dom, int mode, const double* u, double scale, double* y, hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, scale, 1);
+  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, scale, 1);
 }
 
 // P1 mass: the six triangles around vertex (i, j) of the same-diagonal grid,
 // each of area h^2/2, contribute h^2/24 (2 g_i + g_a + g_b) when inside.
-__global__ __launch_bounds__(256) void k_mass_p(int N, const double* __restrict__ g, double* gp) {
+__global__ __launch_bounds__(256) void k_mass_p(int N, int dom, const double* __restrict__ g, double* gp) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= (N + 1) * (N + 1)) return;
   const int i = e % (N + 1), j = e / (N + 1), NP = N + 1;
   auto G = [&](int ii, int jj) { return g[(size_t)jj * NP + ii]; };
-  auto sq = [&](int si, int sj) { return si >= 0 && si < N && sj >= 0 && sj < N; };
+  auto sq = [&](int si, int sj) { return dom_sq(N, dom, si, sj); };
   const double gi = G(i, j);
   double s = 0.0;
   if (sq(i - 1, j - 1)) {
@@ -765,9 +766,9 @@ __global__ __launch_bounds__(256) void k_mass_p(int N, const double* __restrict_
   gp[e] = s / (24.0 * (double)N * (double)N);
 }
 
-void launch_mass_p(int N, const double* g, double* gp, hipStream_t s) {
+void launch_mass_p(int N, int dom, const double* g, double* gp, hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_mass_p<<<(n + 255) / 256, 256, 0, s>>>(N, g, gp);
+  k_mass_p<<<(n + 255) / 256, 256, 0, s>>>(N, dom, g, gp);
 }
 
 // ---------------------------------------------------------------------------
@@ -780,7 +781,7 @@ int dot_blocks(int N, int which) {
   return (int)((n + 256 * DOT_PER_THREAD - 1) / (256 * DOT_PER_THREAD));
 }
 
-__global__ __launch_bounds__(256) void k_dot_partial(int N, int which, const double* __restrict__ a,
+__global__ __launch_bounds__(256) void k_dot_partial(int N, int dom, int which, const double* __restrict__ a,
                                                      const double* __restrict__ b, double* partials) {
   __shared__ double red[4];
   const int M = 2 * N + 1;
@@ -789,11 +790,12 @@ __global__ __launch_bounds__(256) void k_dot_partial(int N, int which, const dou
   for (int k = 0; k < DOT_PER_THREAD; ++k) {
     const int64_t e = (int64_t)blockIdx.x * 256 * DOT_PER_THREAD + k * 256 + threadIdx.x;
     if (e < n) {
-      bool ok = true;
+      bool ok;
       if (which == 0) {
         const int q = (int)(e % ((int64_t)M * M));
-        const int aa = q % M, bb = q / M;
-        ok = aa > 0 && aa < 2 * N && bb > 0 && bb < 2 * N;
+        ok = dom_u(N, dom, q % M, q / M);
+      } else {
+        ok = dom_p(N, dom, (int)(e % (N + 1)), (int)(e / (N + 1)));
       }
       if (ok) s += a[e] * b[e];
     }
@@ -815,10 +817,10 @@ void launch_reduce(const double* partials, int np, double* out, hipStream_t s) {
   k_reduce_final<<<1, 256, 0, s>>>(partials, np, out);
 }
 
-void launch_dot(int N, int which, const double* a, const double* b, double* partials,
+void launch_dot(int N, int dom, int which, const double* a, const double* b, double* partials,
                 double* out, hipStream_t s) {
   const int nb = dot_blocks(N, which);
-  k_dot_partial<<<nb, 256, 0, s>>>(N, which, a, b, partials);
+  k_dot_partial<<<nb, 256, 0, s>>>(N, dom, which, a, b, partials);
   k_reduce_final<<<1, 256, 0, s>>>(partials, nb, out);
 }
 

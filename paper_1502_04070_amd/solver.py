@@ -46,6 +46,16 @@ def _apply_damping(set_level, damping):
                   sigmas[level] if sigmas is not None else None)
 
 
+def _set_domain(params, domain):
+    """"square": the unit square; "l_shape": the unit square without
+    [1/2, 1]^2 (needs an even n0).  The lattice layouts are those of the
+    square; entries at points outside the domain are ignored and written zero
+    or left as they were."""
+    if domain not in _lib.DOMAINS:
+        raise ValueError(f"domain must be one of {list(_lib.DOMAINS)}")
+    params.domain = _lib.DOMAINS[domain]
+
+
 def _set_schedule(params, schedule):
     """Launch schedule of the fused kernels (see smg_params); None: defaults."""
     for k, v in (schedule or {}).items():
@@ -56,12 +66,13 @@ def _set_schedule(params, schedule):
 
 class Hierarchy:
     """A multigrid hierarchy of the generalized Stokes system on the unit square
-    (uniformly refined same-diagonal grid, Taylor-Hood P2-P1)."""
+    or the L-shaped domain (uniformly refined same-diagonal grid, Taylor-Hood
+    P2-P1)."""
 
     def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
                  sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
                  n0: int = 2, fused: bool = True, device=None, schedule: dict | None = None,
-                 damping: dict | None = None):
+                 damping: dict | None = None, domain: str = "square"):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -74,7 +85,8 @@ class Hierarchy:
         self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma),
                                      int(nu_pre), int(nu_post), int(gamma), int(n0), 0 if fused else 1)
         _set_schedule(self.params, schedule)
-        self.N, self.beta, self.smoother = int(N), float(beta), smoother
+        _set_domain(self.params, domain)
+        self.N, self.beta, self.smoother, self.domain = int(N), float(beta), smoother, domain
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.smg_setup(self.N, self.beta, C.byref(self.params), C.byref(h)),
@@ -92,6 +104,7 @@ class Hierarchy:
         self = cls.__new__(cls)
         self.lib, self.h, self.params = lib, C.c_void_p(handle), params
         self.N, self.beta, self.smoother, self.device = N, beta, smoother, device
+        self.domain = next(k for k, v in _lib.DOMAINS.items() if v == params.domain)
         self._owned = False
         self.nlevels = lib.smg_num_levels(self.h)
         self.L = self.nlevels - 1
@@ -313,7 +326,7 @@ class Batch:
 
     def __init__(self, Ns, betas, smoother: str = "ne", tau: float | None = None, sigma: float = 0.8,
                  nu_pre: int = 2, nu_post: int = 2, gamma: int = 1, n0: int = 2,
-                 schedule: dict | None = None, damping: dict | None = None):
+                 schedule: dict | None = None, damping: dict | None = None, domain: str = "square"):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU")
@@ -324,6 +337,7 @@ class Batch:
         self.params = _lib.SmgParams(_lib.SMOOTHERS[smoother], float(tau), float(sigma), int(nu_pre),
                                      int(nu_post), int(gamma), int(n0), 0)
         _set_schedule(self.params, schedule)
+        _set_domain(self.params, domain)
         n = len(Ns)
         Na = (C.c_int * n)(*[int(v) for v in Ns])
         Ba = (C.c_double * n)(*[float(v) for v in betas])

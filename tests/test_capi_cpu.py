@@ -42,7 +42,7 @@ def test_default_params(lib):
     p = _lib.SmgParams()
     assert lib.smg_default_params(C.byref(p)) == 0
     assert (p.smoother, p.tau, p.sigma, p.nu_pre, p.nu_post, p.gamma, p.n0, p.unfused) == (0, 0.35, 0.8, 2, 2, 1, 2, 0)
-    assert (p.fuse_depth, p.coarse_max_n, p.tile_x) == (0, 0, 0)
+    assert (p.fuse_depth, p.coarse_max_n, p.tile_x, p.domain) == (0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("N,beta,mod,needle", [
@@ -58,6 +58,8 @@ def test_default_params(lib):
     (8, 1.0, {"fuse_depth": 3}, "fuse_depth"),
     (8, 1.0, {"tile_x": 12}, "tile_x"),
     (8, 1.0, {"coarse_max_n": -2}, "coarse_max_n"),
+    (8, 1.0, {"domain": 5}, "domain"),
+    (12, 1.0, {"domain": 1, "n0": 3}, "even n0"),
 ])
 def test_setup_rejects_bad_arguments(lib, N, beta, mod, needle):
     p = _lib.SmgParams()
