@@ -18,8 +18,9 @@ LIB = os.path.join(HERE, "libstokesmg.so")
 SOURCES = ["smg_kernels.hip", "smg_fused.hip", "smg_capi.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
+OBJDIR = os.path.join(HERE, "_build")
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -33,11 +34,26 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    """Regenerate the stencil header, compile every translation unit in
+    parallel (each launches only kernels it defines, so no relocatable device
+    code is needed) and link the shared library."""
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_stencils.py"),
                            os.path.join(CSRC, "stencils.inc")], stdout=subprocess.DEVNULL)
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        objs.append(obj)
+        procs.append((src, subprocess.Popen(cmd)))
+    failed = [src for src, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc {' '.join(failed)}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -26,7 +26,8 @@ TileShape ne_tile_shape(int N);
 template <class T>
 void launch_ne2(const NEJob<T>& J, bool zero_guess, bool prolong, hipStream_t s);
 template <class T>
-void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zero_guess, bool prolong, hipStream_t s);
+void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zero_guess, bool prolong, int dom,
+                  hipStream_t s);
 int ne_tiles(int N);
 template <class T>
 void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, int tile_x, hipStream_t s);
@@ -87,12 +88,12 @@ void launch_project_check(const double* mpart, const double* rpart, int np, int 
 // ---------------------------------------------------------------------------
 
 template <class T>
-void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro,
+void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, int dom,
                  hipStream_t s);
 template <class T>
-void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, hipStream_t s);
+void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, int dom, hipStream_t s);
 template <class T>
-void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s);
+void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, int dom, hipStream_t s);
 
 // projection + convergence test per job (one job per instance)
 struct PCJob {

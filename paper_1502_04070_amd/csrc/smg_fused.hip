@@ -81,7 +81,7 @@ __device__ __forceinline__ T pro_p1(const T* zp, int Nc, int i, int j) {
 // k_ne: one fused normal-equation step on a TX x TY tile of squares
 // ---------------------------------------------------------------------------
 
-template <class T, int TX, int TY, bool ZG, bool PRO>
+template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   constexpr int NT = 2 * TX * TY;
   constexpr int XW = 2 * TX + 8, XH = 2 * TY + 8;      // x: lattice origin (2 i0 - 4, 2 j0 - 4)
@@ -97,7 +97,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   const int ntx = (N + TX) / TX;
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
-  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
 
   // Every global input the workgroup needs is requested before the first
   // wait: the done flag, this thread's stage-1 right-hand side and Shat^-1
@@ -116,7 +116,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) f1[2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
   }
-  const bool inp1 = act1 && dom_p(N, J.L.dom, i1, j1);
+  const bool inp1 = act1 && dom_p(N, DOM, i1, j1);
   f1[8] = inp1 ? J.fp[(size_t)j1 * NP + i1] : T(0);
   if (inp1) s1 = J.L.sinv[(size_t)j1 * NP + i1];
   T s2 = T(0);
@@ -144,7 +144,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
           for (int dA = 0; dA < 3; ++dA) {
             const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = dom_u(Nc, J.L.dom, A, B)
+            z[dB][dA] = dom_u(Nc, DOM, A, B)
                             ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
           }
         auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
@@ -173,7 +173,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         const int li = e % XPW, lj = e / XPW;
         const int i = i0 - 2 + li, j = j0 - 2 + lj;
         T v = T(0);
-        if (dom_p(N, J.L.dom, i, j)) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
+        if (dom_p(N, DOM, i, j)) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
         sxp[e] = v;
       }
     } else {
@@ -188,7 +188,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
       for (int e = tid; e < XPW * XPH; e += NT) {
         const int li = e % XPW, lj = e / XPW;
         const int i = i0 - 2 + li, j = j0 - 2 + lj;
-        sxp[e] = dom_p(N, J.L.dom, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+        sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
       }
     }
     __syncthreads();
@@ -293,37 +293,47 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   }
 }
 
-template <class T, int TX, int TY, bool ZG, bool PRO>
+// The domain is a template parameter of every fused kernel (chosen by the
+// host launchers): a run-time test would cost the square's kernels a few
+// percent, and two instantiations inside one kernel would double its static
+// LDS.
+template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
-  ne_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
+  ne_tile<T, TX, TY, ZG, PRO, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK>
+template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK, int DOM>
 __global__ __launch_bounds__(2 * TX* TY) void k_ne_b(const JobArg<NEJob<T>> A) {
   int tile;
   const NEJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
-  ne_tile<T, TX, TY, ZG, PRO>(J, tile);
+  ne_tile<T, TX, TY, ZG, PRO, DOM>(J, tile);
 }
 
-template <class T, int TX, int TY, bool PACK>
+template <class T, int TX, int TY, bool PACK, int DOM>
 static void launch_ne_b_shape(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
-  if (zg) k_ne_b<T, TX, TY, true, false, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
-  else if (pro) k_ne_b<T, TX, TY, false, true, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
-  else k_ne_b<T, TX, TY, false, false, PACK><<<nb, 2 * TX * TY, 0, s>>>(A);
+  if (zg) k_ne_b<T, TX, TY, true, false, PACK, DOM><<<nb, 2 * TX * TY, 0, s>>>(A);
+  else if (pro) k_ne_b<T, TX, TY, false, true, PACK, DOM><<<nb, 2 * TX * TY, 0, s>>>(A);
+  else k_ne_b<T, TX, TY, false, false, PACK, DOM><<<nb, 2 * TX * TY, 0, s>>>(A);
+}
+
+template <class T, int DOM>
+static void launch_ne_b_dom(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, hipStream_t s) {
+  if (tx == 16) {
+    if (A.n > 0) launch_ne_b_shape<T, 16, 8, true, DOM>(A, nb, zg, pro, s);
+    else launch_ne_b_shape<T, 16, 8, false, DOM>(A, nb, zg, pro, s);
+  } else {
+    if (A.n > 0) launch_ne_b_shape<T, 8, 8, true, DOM>(A, nb, zg, pro, s);
+    else launch_ne_b_shape<T, 8, 8, false, DOM>(A, nb, zg, pro, s);
+  }
 }
 
 template <class T>
-void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, hipStream_t s) {
-  if (tx == 16) {
-    if (A.n > 0) launch_ne_b_shape<T, 16, 8, true>(A, nb, zg, pro, s);
-    else launch_ne_b_shape<T, 16, 8, false>(A, nb, zg, pro, s);
-  } else {
-    if (A.n > 0) launch_ne_b_shape<T, 8, 8, true>(A, nb, zg, pro, s);
-    else launch_ne_b_shape<T, 8, 8, false>(A, nb, zg, pro, s);
-  }
+void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_ne_b_dom<T, SMG_DOM_LSHAPE>(A, nb, tx, zg, pro, s);
+  else launch_ne_b_dom<T, SMG_DOM_SQUARE>(A, nb, tx, zg, pro, s);
 }
-template void launch_ne_b<double>(const JobArg<NEJob<double>>&, int, int, bool, bool, hipStream_t);
-template void launch_ne_b<float>(const JobArg<NEJob<float>>&, int, int, bool, bool, hipStream_t);
+template void launch_ne_b<double>(const JobArg<NEJob<double>>&, int, int, bool, bool, int, hipStream_t);
+template void launch_ne_b<float>(const JobArg<NEJob<float>>&, int, int, bool, bool, int, hipStream_t);
 
 TileShape ne_tile_shape(int N) {
   if (N >= 128) return {16, 8};
@@ -335,23 +345,29 @@ int ne_tiles(int N) {
   return ((N + t.tx) / t.tx) * ((N + t.ty) / t.ty);
 }
 
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, int DOM>
 static void launch_ne_shape(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
   const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
   if (zg)
-    k_ne<T, TX, TY, true, false><<<nb, 2 * TX * TY, 0, s>>>(J);
+    k_ne<T, TX, TY, true, false, DOM><<<nb, 2 * TX * TY, 0, s>>>(J);
   else if (pro)
-    k_ne<T, TX, TY, false, true><<<nb, 2 * TX * TY, 0, s>>>(J);
+    k_ne<T, TX, TY, false, true, DOM><<<nb, 2 * TX * TY, 0, s>>>(J);
   else
-    k_ne<T, TX, TY, false, false><<<nb, 2 * TX * TY, 0, s>>>(J);
+    k_ne<T, TX, TY, false, false, DOM><<<nb, 2 * TX * TY, 0, s>>>(J);
+}
+
+template <class T, int DOM>
+static void launch_ne_dom(const NEJob<T>& J, bool zg, bool pro, int tx, hipStream_t s) {
+  if ((tx ? tx : ne_tile_shape(J.L.N).tx) == 16)
+    launch_ne_shape<T, 16, 8, DOM>(J, zg, pro, s);
+  else
+    launch_ne_shape<T, 8, 8, DOM>(J, zg, pro, s);
 }
 
 template <class T>
 void launch_ne(const NEJob<T>& J, bool zg, bool pro, int tx, hipStream_t s) {
-  if ((tx ? tx : ne_tile_shape(J.L.N).tx) == 16)
-    launch_ne_shape<T, 16, 8>(J, zg, pro, s);
-  else
-    launch_ne_shape<T, 8, 8>(J, zg, pro, s);
+  if (J.L.dom == SMG_DOM_LSHAPE) launch_ne_dom<T, SMG_DOM_LSHAPE>(J, zg, pro, tx, s);
+  else launch_ne_dom<T, SMG_DOM_SQUARE>(J, zg, pro, tx, s);
 }
 template void launch_ne<double>(const NEJob<double>&, bool, bool, int, hipStream_t);
 template void launch_ne<float>(const NEJob<float>&, bool, bool, int, hipStream_t);
@@ -369,7 +385,7 @@ template void launch_ne<float>(const NEJob<float>&, bool, bool, int, hipStream_t
 // velocity space and outside the grid.  Each value is computed by the same
 // expressions as in two single steps.
 
-template <class T, int TX, int TY, bool ZG, bool PRO>
+template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   constexpr int NT = 4 * TX * TY;
   constexpr int W4 = 2 * TX + 16, H4 = 2 * TY + 16, PW4 = TX + 8, PH4 = TY + 8;   // X0: tile + 4
@@ -391,8 +407,8 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
   const T tau = J.tau;
-  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
-  auto inside = [&](int i, int j) { return dom_p(N, J.L.dom, i, j); };
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
+  auto inside = [&](int i, int j) { return dom_p(N, DOM, i, j); };
 
   // ---- stage 0: F and Shat^-1 on the tile + 3, the iterate on the tile + 4
   const int dn = J.done ? *J.done : 0;
@@ -426,7 +442,7 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
           for (int dA = 0; dA < 3; ++dA) {
             const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = dom_u(Nc, J.L.dom, A, B)
+            z[dB][dA] = dom_u(Nc, DOM, A, B)
                             ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
           }
         auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
@@ -589,48 +605,60 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   }
 }
 
-template <class T, int TX, int TY, bool ZG, bool PRO>
+template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __global__ __launch_bounds__(4 * TX* TY) void k_ne2(NEJob<T> J) {
-  ne2_tile<T, TX, TY, ZG, PRO>(J, xcd_remap(blockIdx.x, gridDim.x));
+  ne2_tile<T, TX, TY, ZG, PRO, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK>
+template <class T, int TX, int TY, bool ZG, bool PRO, bool PACK, int DOM>
 __global__ __launch_bounds__(4 * TX* TY) void k_ne2_b(const JobArg<NEJob<T>> A) {
   int tile;
   const NEJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
-  ne2_tile<T, TX, TY, ZG, PRO>(J, tile);
+  ne2_tile<T, TX, TY, ZG, PRO, DOM>(J, tile);
+}
+
+template <class T, int DOM>
+static void launch_ne2_dom(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
+  const int nb = ((J.L.N + 8) / 8) * ((J.L.N + 8) / 8);
+  if (zg) k_ne2<T, 8, 8, true, false, DOM><<<nb, 256, 0, s>>>(J);
+  else if (pro) k_ne2<T, 8, 8, false, true, DOM><<<nb, 256, 0, s>>>(J);
+  else k_ne2<T, 8, 8, false, false, DOM><<<nb, 256, 0, s>>>(J);
 }
 
 template <class T>
 void launch_ne2(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
-  const int nb = ((J.L.N + 8) / 8) * ((J.L.N + 8) / 8);
-  if (zg) k_ne2<T, 8, 8, true, false><<<nb, 256, 0, s>>>(J);
-  else if (pro) k_ne2<T, 8, 8, false, true><<<nb, 256, 0, s>>>(J);
-  else k_ne2<T, 8, 8, false, false><<<nb, 256, 0, s>>>(J);
+  if (J.L.dom == SMG_DOM_LSHAPE) launch_ne2_dom<T, SMG_DOM_LSHAPE>(J, zg, pro, s);
+  else launch_ne2_dom<T, SMG_DOM_SQUARE>(J, zg, pro, s);
 }
 template void launch_ne2<double>(const NEJob<double>&, bool, bool, hipStream_t);
 template void launch_ne2<float>(const NEJob<float>&, bool, bool, hipStream_t);
 
-template <class T, bool PACK>
+template <class T, bool PACK, int DOM>
 static void launch_ne2_b_pack(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
-  if (zg) k_ne2_b<T, 8, 8, true, false, PACK><<<nb, 256, 0, s>>>(A);
-  else if (pro) k_ne2_b<T, 8, 8, false, true, PACK><<<nb, 256, 0, s>>>(A);
-  else k_ne2_b<T, 8, 8, false, false, PACK><<<nb, 256, 0, s>>>(A);
+  if (zg) k_ne2_b<T, 8, 8, true, false, PACK, DOM><<<nb, 256, 0, s>>>(A);
+  else if (pro) k_ne2_b<T, 8, 8, false, true, PACK, DOM><<<nb, 256, 0, s>>>(A);
+  else k_ne2_b<T, 8, 8, false, false, PACK, DOM><<<nb, 256, 0, s>>>(A);
+}
+
+template <class T, int DOM>
+static void launch_ne2_b_dom(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
+  if (A.n > 0) launch_ne2_b_pack<T, true, DOM>(A, nb, zg, pro, s);
+  else launch_ne2_b_pack<T, false, DOM>(A, nb, zg, pro, s);
 }
 
 template <class T>
-void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, hipStream_t s) {
-  if (A.n > 0) launch_ne2_b_pack<T, true>(A, nb, zg, pro, s);
-  else launch_ne2_b_pack<T, false>(A, nb, zg, pro, s);
+void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_ne2_b_dom<T, SMG_DOM_LSHAPE>(A, nb, zg, pro, s);
+  else launch_ne2_b_dom<T, SMG_DOM_SQUARE>(A, nb, zg, pro, s);
 }
-template void launch_ne2_b<double>(const JobArg<NEJob<double>>&, int, bool, bool, hipStream_t);
-template void launch_ne2_b<float>(const JobArg<NEJob<float>>&, int, bool, bool, hipStream_t);
+template void launch_ne2_b<double>(const JobArg<NEJob<double>>&, int, bool, bool, int, hipStream_t);
+template void launch_ne2_b<float>(const JobArg<NEJob<float>>&, int, bool, bool, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // k_resid_restrict: F_c = P^T (F - A x) on an 8 x 8 tile of coarse squares
 // ---------------------------------------------------------------------------
 
-template <class T>
+template <class T, int DOM>
 __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   constexpr int TC = 8, NT = 256;
   constexpr int XW = 4 * TC + 10;      // x: fine lattice origin (4 I0 - 6, 4 J0 - 6)
@@ -647,7 +675,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   const int ntx = (Nc + TC) / TC;
   const int I0 = (tile % ntx) * TC, J0 = (tile / ntx) * TC;
   const int tid = threadIdx.x;
-  auto interior = [&](int a, int b) { return dom_u(N, J.L.dom, a, b); };
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
   // the done flag and this thread's stage-1 right-hand sides (at most two
   // squares per thread) are requested together with the iterate window
   static_assert(NC1 * NC1 <= 2 * NT, "at most two stage-1 squares per thread");
@@ -665,7 +693,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) f1[it][2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
     }
-    const bool inp = act && dom_p(N, J.L.dom, i, j);
+    const bool inp = act && dom_p(N, DOM, i, j);
     f1[it][8] = inp ? J.fp[(size_t)j * NP + i] : T(0);
   }
   for (int e = tid; e < XW * XW; e += NT) {
@@ -679,7 +707,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   for (int e = tid; e < XPW * XPW; e += NT) {
     const int li = e % XPW, lj = e / XPW;
     const int i = 2 * I0 - 3 + li, j = 2 * J0 - 3 + lj;
-    sxp[e] = dom_p(N, J.L.dom, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+    sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
   }
   __syncthreads();
   if (dn) return;   // uniform across the workgroup
@@ -700,7 +728,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) sr[c][2 * cj + DB][2 * ci + DA] = in ? f1[it][2 * cls + c] - y[2 * cls + c] : T(0);
     }
-    const bool inp = dom_p(N, J.L.dom, i, j);
+    const bool inp = dom_p(N, DOM, i, j);
     srp[cj * RPW + ci] = inp ? f1[it][8] - y[8] : T(0);
   }
   __syncthreads();
@@ -712,7 +740,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     const int CA = cls & 1, CB = cls >> 1;
     const int A = 2 * I + CA, B = 2 * Jc + CB;
     if (A <= 2 * Nc && B <= 2 * Nc) {
-      const bool in = dom_u(Nc, J.L.dom, A, B);
+      const bool in = dom_u(Nc, DOM, A, B);
       const int la = 4 * tx + 2 * CA + 4, lb = 4 * ty + 2 * CB + 4;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -732,38 +760,45 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     if (cls == 3) {
       auto Rp = [&](int di, int dj) -> T { return srp[(2 * ty + 2 + dj) * RPW + (2 * tx + 2 + di)]; };
       J.cp[(size_t)Jc * NPc + I] =
-          dom_p(Nc, J.L.dom, I, Jc)
+          dom_p(Nc, DOM, I, Jc)
               ? Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1))
               : T(0);
     }
   }
 }
 
-template <class T>
+template <class T, int DOM>
 __global__ __launch_bounds__(256) void k_resid_restrict(RRJob<T> J) {
-  rr_tile<T>(J, xcd_remap(blockIdx.x, gridDim.x));
+  rr_tile<T, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <class T, bool PACK>
+template <class T, bool PACK, int DOM>
 __global__ __launch_bounds__(256) void k_rr_b(const JobArg<RRJob<T>> A) {
   int tile;
   const RRJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
-  rr_tile<T>(J, tile);
+  rr_tile<T, DOM>(J, tile);
+}
+
+template <class T, int DOM>
+static void launch_rr_b_dom(const JobArg<RRJob<T>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_rr_b<T, true, DOM><<<nb, 256, 0, s>>>(A);
+  else k_rr_b<T, false, DOM><<<nb, 256, 0, s>>>(A);
 }
 
 template <class T>
-void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, hipStream_t s) {
-  if (A.n > 0) k_rr_b<T, true><<<nb, 256, 0, s>>>(A);
-  else k_rr_b<T, false><<<nb, 256, 0, s>>>(A);
+void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_rr_b_dom<T, SMG_DOM_LSHAPE>(A, nb, s);
+  else launch_rr_b_dom<T, SMG_DOM_SQUARE>(A, nb, s);
 }
-template void launch_rr_b<double>(const JobArg<RRJob<double>>&, int, hipStream_t);
-template void launch_rr_b<float>(const JobArg<RRJob<float>>&, int, hipStream_t);
+template void launch_rr_b<double>(const JobArg<RRJob<double>>&, int, int, hipStream_t);
+template void launch_rr_b<float>(const JobArg<RRJob<float>>&, int, int, hipStream_t);
 
 template <class T>
 void launch_resid_restrict(const RRJob<T>& J, hipStream_t s) {
   const int Nc = J.L.N / 2;
   const int nb = ((Nc + 8) / 8) * ((Nc + 8) / 8);
-  k_resid_restrict<T><<<nb, 256, 0, s>>>(J);
+  if (J.L.dom == SMG_DOM_LSHAPE) k_resid_restrict<T, SMG_DOM_LSHAPE><<<nb, 256, 0, s>>>(J);
+  else k_resid_restrict<T, SMG_DOM_SQUARE><<<nb, 256, 0, s>>>(J);
 }
 template void launch_resid_restrict<double>(const RRJob<double>&, hipStream_t);
 template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
@@ -776,13 +811,13 @@ template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
 // FP64 stencil rows without spills
 constexpr int CC_THREADS = 768;
 
-template <class T>
+template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle(CoarseJob<T> J) {
   if (J.done && *J.done) return;
-  coarse_body<T>(J);
+  coarse_body<T, DOM>(J);
 }
 
-template <class T>
+template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
   // the job (about 1.4 KB of coefficients and pointers) is staged in LDS once;
   // read through global memory, every coefficient access inside the phases
@@ -795,15 +830,16 @@ __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T
   }
   __syncthreads();
   if (sj.done && *sj.done) return;
-  coarse_body<T>(sj);
+  coarse_body<T, DOM>(sj);
 }
 
 template <class T>
-void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, hipStream_t s) {
-  k_coarse_cycle_b<T><<<njobs, CC_THREADS, lds, s>>>(jobs);
+void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) k_coarse_cycle_b<T, SMG_DOM_LSHAPE><<<njobs, CC_THREADS, lds, s>>>(jobs);
+  else k_coarse_cycle_b<T, SMG_DOM_SQUARE><<<njobs, CC_THREADS, lds, s>>>(jobs);
 }
-template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, hipStream_t);
-template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, hipStream_t);
+template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, int, hipStream_t);
+template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, int, hipStream_t);
 
 size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
   size_t tot = 0;
@@ -817,7 +853,8 @@ size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
 template <class T>
 int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s) {
   const size_t lds = coarse_cycle_lds(J.n0, J.Lc, sizeof(T));
-  k_coarse_cycle<T><<<1, CC_THREADS, lds, s>>>(J);
+  if (J.L[0].dom == SMG_DOM_LSHAPE) k_coarse_cycle<T, SMG_DOM_LSHAPE><<<1, CC_THREADS, lds, s>>>(J);
+  else k_coarse_cycle<T, SMG_DOM_SQUARE><<<1, CC_THREADS, lds, s>>>(J);
   return 0;
 }
 template int launch_coarse_cycle<double>(const CoarseJob<double>&, hipStream_t);
@@ -825,11 +862,15 @@ template int launch_coarse_cycle<float>(const CoarseJob<float>&, hipStream_t);
 
 template <class T>
 int coarse_cycle_allow_lds(size_t bytes) {
-  int e1 = (int)hipFuncSetAttribute((const void*)k_coarse_cycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)bytes);
-  int e2 = (int)hipFuncSetAttribute((const void*)k_coarse_cycle_b<T>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return e1 != 0 ? e1 : e2;
+  const void* fns[4] = {(const void*)k_coarse_cycle<T, SMG_DOM_SQUARE>,
+                        (const void*)k_coarse_cycle_b<T, SMG_DOM_SQUARE>,
+                        (const void*)k_coarse_cycle<T, SMG_DOM_LSHAPE>,
+                        (const void*)k_coarse_cycle_b<T, SMG_DOM_LSHAPE>};
+  for (const void* f : fns) {
+    const int e = (int)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != 0) return e;
+  }
+  return 0;
 }
 template int coarse_cycle_allow_lds<double>(size_t);
 template int coarse_cycle_allow_lds<float>(size_t);

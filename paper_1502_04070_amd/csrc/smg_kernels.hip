@@ -109,7 +109,7 @@ struct Flags {
   }
 };
 
-template <int CLS, unsigned F, class T, int WX, int WY, int PX, int PY>
+template <int CLS, unsigned F, int DOM, class T, int WX, int WY, int PX, int PY>
 __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY][WX],
                                               T (*sp)[PX], int tx, int ty, int i, int j,
                                               double& nrm) {
@@ -118,7 +118,7 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
   const int N = J.L.N, M = 2 * N + 1;
   const int a = 2 * i + DA, b = 2 * j + DB;
   if (a > 2 * N || b > 2 * N) return;
-  const bool interior = dom_u(N, J.L.dom, a, b);
+  const bool interior = dom_u(N, DOM >= 0 ? DOM : J.L.dom, a, b);
   const int la = 2 * tx + 2 + DA, lb = 2 * ty + 2 + DB;
   const bool hu = FL::on(F_IN_U, J.in_u);
   const bool hp = FL::on(F_IN_P, J.in_p);
@@ -141,7 +141,9 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
   }
 }
 
-template <class T, int TX, int TY, unsigned F>
+// DOM: the domain, or -1 to read it from the job (the stencil kernels take
+// the run-time test; the fused kernels are instantiated per domain)
+template <class T, int TX, int TY, unsigned F, int DOM>
 __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   using FL = Flags<F>;
   constexpr int NT = TX * TY;
@@ -151,6 +153,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   __shared__ T sp[PY][PX];
   __shared__ double red[NT / 64];
   const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int dom = DOM >= 0 ? DOM : J.L.dom;
   const int ntx = (N + TX) / TX;
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
@@ -162,7 +165,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
     for (int e = tid; e < WX * WY; e += NT) {
       const int la = e % WX, lb = e / WX;
       const int a = 2 * i0 - 2 + la, b = 2 * j0 - 2 + lb;
-      const bool in = dom_u(N, J.L.dom, a, b);
+      const bool in = dom_u(N, dom, a, b);
       const size_t g = (size_t)b * M + a;
       su[0][lb][la] = in ? J.in_u[g] : T(0);
       su[1][lb][la] = in ? J.in_u[(size_t)M * M + g] : T(0);
@@ -173,7 +176,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       const int li = e % PX, lj = e / PX;
       const int i = i0 - 1 + li, j = j0 - 1 + lj;
       T v = T(0);
-      if (dom_p(N, J.L.dom, i, j)) {
+      if (dom_p(N, dom, i, j)) {
         v = J.in_p[(size_t)j * NP + i];
         if (FL::on(F_PSUB, J.in_p_sub)) v -= J.in_p_sub[(size_t)j * NP + i];
       }
@@ -186,10 +189,10 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   double nrm = 0.0;
   if (i <= N && j <= N) {
     if (rows_u) {
-      velocity_node<0, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<1, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<2, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<3, F, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<0, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<1, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<2, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<3, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
     }
     if (rows_p) {
       const int la = 2 * tx + 2, lb = 2 * ty + 2;
@@ -198,7 +201,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       const T y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
       const size_t g = (size_t)j * NP + i;
       // vertices outside the domain carry no pressure unknown: zero row
-      const bool pin = dom_p(N, J.L.dom, i, j);
+      const bool pin = dom_p(N, dom, i, j);
       const T r = pin ? (FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y : T(0);
       if (FL::on(F_PARTIAL, J.partial)) nrm += (double)r * (double)r;
       if (FL::on(F_OUT_P, J.out_p)) {
@@ -215,7 +218,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
     // pressure mean pieces of in_p over the owned vertices
     double w = 0.0, wp = 0.0;
     if (i <= N && j <= N) {
-      w = p1_count_w(N, J.L.dom, i, j);
+      w = p1_count_w(N, dom, i, j);
       wp = w * (double)sp[ty + 1][tx + 1];
     }
     __syncthreads();
@@ -232,7 +235,7 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
 template <class T, int TX, int TY, unsigned F>
 __global__ __launch_bounds__(TX* TY) void k_stencil(StencilJob<T> J) {
   if (J.done && *J.done) return;
-  stencil_tile<T, TX, TY, F>(J, xcd_swizzle(blockIdx.x, gridDim.x));
+  stencil_tile<T, TX, TY, F, -1>(J, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 TileShape stencil_tile(int N) {
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(TX* TY) void k_stencil_b(const JobArg<StencilJob<T>
   int tile;
   const StencilJob<T> J = block_job<PACK>(A, xcd_swizzle(blockIdx.x, gridDim.x), tile);
   if (J.done && *J.done) return;
-  stencil_tile<T, TX, TY, F>(J, tile);
+  stencil_tile<T, TX, TY, F, -1>(J, tile);
 }
 
 template <class T, int TX, int TY>
