@@ -96,10 +96,16 @@ typedef struct {
                        analysis does not); needs an even n0.  The layouts stay
                        those of the square: entries at points outside the
                        domain are never read, and every entry point writes zero
-                       there or leaves them as they were.                      */
+                       there or leaves them as they were.
+                       SMG_DOMAIN_UNIONJACK: the unit square on the grid of the
+                       experiments of Section 6 (the coarsest 2 x 2 grid with
+                       the diagonals meeting at the centre, refined
+                       uniformly); needs an even n0.  Runs the unfused
+                       kernels (unfused is set to 1) and single hierarchies
+                       only (no batches).                                      */
 } smg_params;
 
-enum { SMG_DOMAIN_SQUARE = 0, SMG_DOMAIN_LSHAPE = 1 };
+enum { SMG_DOMAIN_SQUARE = 0, SMG_DOMAIN_LSHAPE = 1, SMG_DOMAIN_UNIONJACK = 2 };
 
 /* Defaults: normal equation, tau = 0.35, sigma = 0.8, V(2,2), n0 = 2, fused,
  * default launch schedule. */
@@ -189,6 +195,29 @@ int smg_project_dual(smg_t h, int level, double* v, smg_stream_t s);
  * followed by the mean projection; in place on (u, p). */
 int smg_cycle(smg_t h, const double* fu, const double* gp, double* u, double* p,
               smg_stream_t s);
+
+/*
+ * Error measure of the experiments (Section 6) on the finest level:
+ *   *out = ||e||_L = (sum Ahat_k e_u,k^2 + sum Shat_q e_p,q^2)^(1/2),
+ * e = (u, p) - (us, ps), its pressure part made mean-free (int e_p = 0)
+ * first; Ahat = diag A, Shat = diag(B Ahat^-1 B^T).  Device vectors in, HOST
+ * double out; synchronizes the stream.  Errors: SMG_EINVAL, SMG_EHIP.
+ */
+int smg_error_norm(smg_t h, const double* u, const double* p, const double* us, const double* ps,
+                   double* out, smg_stream_t s);
+
+/*
+ * The measurement protocol of Section 6: starting from the (u, p) given,
+ * repeat iterates on F = (fu, gp) (normally calA (us, ps), see smg_apply)
+ * until ||x - x*||_L <= eps ||x0 - x*||_L, with x* = (us, ps).  iters (HOST)
+ * receives the number of iterates and rate (HOST) the mean reduction factor
+ * (||e_n|| / ||e_0||)^(1/n); either may be NULL.  One synchronization per
+ * iterate.  Returns SMG_OK, SMG_NOCONV (maxit reached), SMG_DIVERGED (the
+ * error grew by 1e6) or SMG_ENONFINITE (soft), or a hard error.
+ */
+int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* us, const double* ps,
+                    double eps, int maxit, double* u, double* p, int* iters, double* rate,
+                    smg_stream_t s);
 
 /*
  * Solve calA x = F on the finest level to ||F - calA x|| <= rtol ||F|| (2-norm

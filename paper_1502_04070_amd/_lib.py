@@ -15,7 +15,7 @@ SMG_OK = 0
 STATUS = {0: "ok", -1: "einval", -2: "ehip", -3: "enomem", -4: "esingular",
           1: "noconv", 2: "diverged", 3: "nonfinite"}
 SMOOTHERS = {"ne": 0, "uzawa": 1}
-DOMAINS = {"square": 0, "l_shape": 1}
+DOMAINS = {"square": 0, "l_shape": 1, "union_jack": 2}
 
 
 class SmgParams(C.Structure):
@@ -55,6 +55,8 @@ SIGNATURES = {
     "smg_cycle": [P, P, P, P, P, P],
     "smg_cycle_f32": [P, P, P, P, P, P],
     "smg_solve": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],
+    "smg_error_norm": [P, P, P, P, P, C.POINTER(D), P],
+    "smg_solve_error": [P, P, P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), P],
     "smg_solve_mixed": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), C.POINTER(D), P],
     "smg_dot": [P, I, I, P, P, P, P],
     "smg_time_kernel": [P, I, I, C.POINTER(D), P],

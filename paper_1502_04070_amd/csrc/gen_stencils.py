@@ -214,6 +214,64 @@ def build():
     return A_TAPS, BT_TAPS, B_TAPS, PRO, RES
 
 
+def square_matrices():
+    """Square-local matrices of one grid square and both diagonal directions
+    (union-jack grid), over the 9 P2 lattice nodes of the square (index
+    3 lb + la, half units (la, lb) in 0..2) and its 4 corners (index 2 pb + pa):
+    K, M (9 x 9), Bx, By (4 x 9), MP (4 x 4, P1 mass), PRO (16 x 9: owned fine
+    point 4 rb + ra of the refined square from the square's nodes), PP (4 x 4:
+    owned fine vertex 2 pb + pa from the corners).  Orientation 0: diagonal
+    from the lower-left to the upper-right corner; 1: the other diagonal, the
+    mirror image x -> 1 - x of orientation 0 (stiffness and mass invariant,
+    the x-derivative changes sign)."""
+    ref = {"L": Tri([(0, 0), (2, 0), (2, 2)], "L"), "U": Tri([(0, 0), (2, 2), (0, 2)], "U")}
+    z9 = lambda: [[Fr(0)] * 9 for _ in range(9)]
+    K0, M0 = z9(), z9()
+    BX0 = [[Fr(0)] * 9 for _ in range(4)]
+    BY0 = [[Fr(0)] * 9 for _ in range(4)]
+    MP0 = [[Fr(0)] * 4 for _ in range(4)]
+    for t in ref.values():
+        _, K, M, Bx, By = local_matrices(t)
+        idx = [n[1] * 3 + n[0] for n in t.nodes]
+        cidx = [(v[1] // 2) * 2 + v[0] // 2 for v in t.verts]
+        for a in range(6):
+            for b in range(6):
+                K0[idx[a]][idx[b]] += K[a][b]
+                M0[idx[a]][idx[b]] += M[a][b]
+        for k in range(3):
+            for b in range(6):
+                BX0[cidx[k]][idx[b]] += Bx[k][b]
+                BY0[cidx[k]][idx[b]] += By[k][b]
+        # P1 mass of the triangle: area/12 (1 + delta_kl), area 1/2 in unit legs
+        for k in range(3):
+            for l in range(3):
+                MP0[cidx[k]][cidx[l]] += Fr(1, 24) * (2 if k == l else 1)
+    mir9 = lambda n: (n // 3) * 3 + (2 - n % 3)
+    mir4 = lambda q: (q // 2) * 2 + (1 - q % 2)
+    K1 = [[K0[mir9(a)][mir9(b)] for b in range(9)] for a in range(9)]
+    M1 = [[M0[mir9(a)][mir9(b)] for b in range(9)] for a in range(9)]
+    BX1 = [[-BX0[mir4(q)][mir9(b)] for b in range(9)] for q in range(4)]
+    BY1 = [[BY0[mir4(q)][mir9(b)] for b in range(9)] for q in range(4)]
+    MP1 = [[MP0[mir4(q)][mir4(r)] for r in range(4)] for q in range(4)]
+    _, _, _, PRO, _ = build()
+    PRO0 = [[Fr(0)] * 9 for _ in range(16)]
+    for (ra, rb), taps in PRO.items():
+        for (dA, dB, w) in taps:
+            PRO0[rb * 4 + ra][dB * 3 + dA] = w
+    PRO1 = [[Fr(0)] * 9 for _ in range(16)]
+    for ra, rb in product(range(4), range(4)):
+        for c in range(9):
+            if ra == 0:                       # the square's left edge: the same 1-D rule
+                PRO1[rb * 4 + ra][c] = PRO0[rb * 4 + ra][c]
+            else:
+                PRO1[rb * 4 + ra][c] = PRO0[rb * 4 + (4 - ra)][mir9(c)]
+    h = Fr(1, 2)
+    PP0 = [[Fr(1), 0, 0, 0], [h, h, 0, 0], [h, 0, h, 0], [h, 0, 0, h]]
+    PP1 = [[Fr(1), 0, 0, 0], [h, h, 0, 0], [h, 0, h, 0], [0, h, h, 0]]
+    return {"K": (K0, K1), "M": (M0, M1), "BX": (BX0, BX1), "BY": (BY0, BY1), "MP": (MP0, MP1),
+            "PRO": (PRO0, PRO1), "PP": (PP0, PP1)}
+
+
 def _lit(fr):
     """C++ literal of an exact rational, converted to the arithmetic type T of
     the code that expands the macro (T must be a type name in scope)."""
@@ -319,6 +377,20 @@ def emit(path):
     for ci, taps in enumerate(RES):
         terms = [f"{_lit(wt)} * R({fa},{fb})" for (fa, fb, wt) in taps]
         w(f"#define SMG_RES_ROW_{CLASS_NAME[ci]}(R) ( " + " + \\\n    ".join(terms) + " )")
+    # square-local matrices of both diagonal directions (union-jack grid)
+    SQ = square_matrices()
+    w("// ---- square-local matrices, orientation 0 (diagonal /) and 1 (diagonal \\) ----")
+    w("// nodes 3 lb + la (half units in the square), corners 2 pb + pa; K, M and")
+    w("// MP in unit legs (M, MP times h^2 and B times h at use); PRO: owned fine")
+    w("// point 4 rb + ra of the refined square from the square's nodes; PP: owned")
+    w("// fine vertex 2 pb + pa from the corners")
+    shapes = {"K": (9, 9), "M": (9, 9), "BX": (4, 9), "BY": (4, 9), "MP": (4, 4), "PRO": (16, 9), "PP": (4, 4)}
+    for name, (r, c) in shapes.items():
+        w(f"constexpr double UJ_{name}[2][{r}][{c}] = {{")
+        for o in range(2):
+            rows = ["{" + ", ".join(_dlit(Fr(v)) for v in row) + "}" for row in SQ[name][o]]
+            w("  {" + ",\n   ".join(rows) + "},")
+        w("};")
     w("}  // namespace smg_stencil")
     with open(path, "w") as fh:
         fh.write("\n".join(L) + "\n")

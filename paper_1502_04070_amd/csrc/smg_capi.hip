@@ -24,6 +24,7 @@
 
 namespace smg {
 #include "stencils.inc"
+#include "smg_uj.h"
 }
 
 using namespace smg;
@@ -101,6 +102,7 @@ struct smg_hier {
   double* red = nullptr;           // reduction scratch
   int red_cap = 0;
   double* fdots = nullptr;         // 2 doubles
+  double* enorm = nullptr;         // 4 doubles (error-measure pieces)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
   // single-workgroup iterate of levels 0..Lc (Lc = -1: not used)
@@ -144,6 +146,8 @@ void make_coef(int N, int dom, double beta, LevelCoef<double>& c, LevelCoef<floa
   c.dom = c32.dom = dom;
   c.h = h;
   c32.h = (float)h;
+  c.bh2 = bh2;
+  c32.bh2 = (float)bh2;
   for (int k = 0; k < 4; ++k) {
     for (int g = 0; g < 5; ++g) {
       c.acoef[k][g] = A_K[k][g] + bh2 * A_M[k][g];
@@ -164,6 +168,32 @@ void host_apply(int N, const LevelCoef<T>& c, const T* u, const T* p, T* yu, T* 
     return dom_u(N, c.dom, a, b) ? u[(size_t)comp * M * M + (size_t)b * M + a] : T(0);
   };
   auto Pg = [&](int i, int j) -> T { return dom_p(N, c.dom, i, j) ? p[(size_t)j * NP + i] : T(0); };
+  if (c.dom == SMG_DOM_UNIONJACK) {
+    // rows summed square by square, as in the kernels
+    for (int j = 0; j < NP; ++j)
+      for (int i = 0; i < NP; ++i) {
+        auto U = [&](int comp, int la, int lb) -> T { return Ug(comp, 2 * i + la, 2 * j + lb); };
+        auto P = [&](int di, int dj) -> T { return Pg(i + di, j + dj); };
+        auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+        for (int cls = 0; cls < 4; ++cls) {
+          const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+          if (a > 2 * N || b > 2 * N) continue;
+          T y0 = T(0), y1 = T(0), d = T(0);
+          if (dom_u(N, c.dom, a, b)) {
+            switch (cls) {
+              case 0: uj_vel_rows<0, T>(c.bh2, h, true, true, U, P, OR, y0, y1, d); break;
+              case 1: uj_vel_rows<1, T>(c.bh2, h, true, true, U, P, OR, y0, y1, d); break;
+              case 2: uj_vel_rows<2, T>(c.bh2, h, true, true, U, P, OR, y0, y1, d); break;
+              default: uj_vel_rows<3, T>(c.bh2, h, true, true, U, P, OR, y0, y1, d); break;
+            }
+          }
+          yu[(size_t)b * M + a] = y0;
+          yu[(size_t)M * M + (size_t)b * M + a] = y1;
+        }
+        yp[(size_t)j * NP + i] = uj_p_row<T>(h, U, OR);
+      }
+    return;
+  }
   for (int comp = 0; comp < 2; ++comp)
     for (int b = 0; b < M; ++b)
       for (int a = 0; a < M; ++a) {
@@ -221,6 +251,18 @@ int build_coarse_inverse(int N0, const LevelCoef<double>& c, std::vector<double>
   }
   for (int k = 0; k < NP * NP; ++k)
     if (!dom_p(N0, c.dom, k % NP, k / NP)) A[(size_t)(2 * nu + k) * nc + (2 * nu + k)] = 1.0;
+  // symmetric equilibration S A S (s_k = 1 / sqrt(max_q |A_kq|)): the blocks
+  // scale like beta h^2, h and h^2, so without it the pivots of the pressure
+  // rows fall below any fixed threshold relative to the largest entry once
+  // beta h^2 is large; the inverse is S (S A S)^-1 S
+  std::vector<double> sc(nc);
+  for (int k = 0; k < nc; ++k) {
+    double rmax = 0.0;
+    for (int q = 0; q < nc; ++q) rmax = std::max(rmax, std::fabs(A[(size_t)k * nc + q]));
+    sc[k] = rmax > 0.0 ? 1.0 / std::sqrt(rmax) : 1.0;
+  }
+  for (int k = 0; k < nc; ++k)
+    for (int q = 0; q < nc; ++q) A[(size_t)k * nc + q] *= sc[k] * sc[q];
   double amax = 0.0;
   for (double v : A) amax = std::max(amax, std::fabs(v));
   // LU with partial pivoting, then solve for the identity
@@ -254,8 +296,8 @@ int build_coarse_inverse(int N0, const LevelCoef<double>& c, std::vector<double>
       for (int q = k + 1; q < nc; ++q) e[k] -= A[(size_t)k * nc + q] * e[q];
       e[k] /= A[(size_t)k * nc + k];
     }
-    // column `col` of the inverse: Inv[row][col] = e[row]; stored at [col * nc + row]
-    for (int row = 0; row < nc; ++row) inv_colmajor[(size_t)col * nc + row] = e[row];
+    // column `col` of the inverse: Inv[row][col] = s_row e[row] s_col; stored at [col * nc + row]
+    for (int row = 0; row < nc; ++row) inv_colmajor[(size_t)col * nc + row] = sc[row] * e[row] * sc[col];
   }
   return SMG_OK;
 }
@@ -731,8 +773,13 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   if (prm.fuse_depth < 0 || prm.fuse_depth > 2) return fail(SMG_EINVAL, "fuse_depth must be 0, 1 or 2");
   if (prm.coarse_max_n < 0) return fail(SMG_EINVAL, "coarse_max_n must be >= 0");
   if (prm.tile_x != 0 && prm.tile_x != 8 && prm.tile_x != 16) return fail(SMG_EINVAL, "tile_x must be 0, 8 or 16");
-  if (prm.domain != SMG_DOM_SQUARE && prm.domain != SMG_DOM_LSHAPE) return fail(SMG_EINVAL, "unknown domain %d", prm.domain);
+  if (prm.domain != SMG_DOM_SQUARE && prm.domain != SMG_DOM_LSHAPE && prm.domain != SMG_DOM_UNIONJACK)
+    return fail(SMG_EINVAL, "unknown domain %d", prm.domain);
   if (prm.domain == SMG_DOM_LSHAPE && prm.n0 % 2) return fail(SMG_EINVAL, "the L-shaped domain needs an even n0");
+  if (prm.domain == SMG_DOM_UNIONJACK && prm.n0 % 2) return fail(SMG_EINVAL, "the union-jack grid needs an even n0");
+  // the fused kernels assume one diagonal direction: the union-jack grid
+  // runs the unfused iterate
+  if (prm.domain == SMG_DOM_UNIONJACK) prm.unfused = 1;
   if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
   int L = 0;
   {
@@ -785,14 +832,16 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     red_need = std::max(red_need, 2 * mean_blocks(Lv.N));
     red_need = std::max(red_need, dot_blocks(Lv.N, 0));
     red_need = std::max(red_need, dot_blocks(Lv.N, 1));
+    red_need = std::max(red_need, enorm_scratch(Lv.N));
   }
   H->red = H->alloc<double>(red_need);
   H->red_cap = red_need;
   H->fdots = H->alloc<double>(2);
+  H->enorm = H->alloc<double>(4);
   H->st = H->alloc<SolveState>(1);
   H->hist_cap = 1000;
   H->hist = H->alloc<double>(H->hist_cap);
-  if (!H->red || !H->fdots || !H->st || !H->hist) { delete H; return fail(SMG_ENOMEM, "scratch"); }
+  if (!H->red || !H->fdots || !H->enorm || !H->st || !H->hist) { delete H; return fail(SMG_ENOMEM, "scratch"); }
   if (hipHostMalloc((void**)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
     H->st_host = nullptr;
     delete H;
@@ -805,8 +854,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
   hipStream_t s = H->cap_stream;
   for (int l = 0; l <= L; ++l) {
     Level& Lv = H->lv[l];
-    launch_shat_inv<double>(Lv.N, H->dom, Lv.c64.adinv, const_cast<double*>(Lv.c64.sinv), s);
-    launch_shat_inv<float>(Lv.N, H->dom, Lv.c32.adinv, const_cast<float*>(Lv.c32.sinv), s);
+    launch_shat_inv<double>(Lv.N, H->dom, Lv.c64.bh2, Lv.c64.adinv, const_cast<double*>(Lv.c64.sinv), s);
+    launch_shat_inv<float>(Lv.N, H->dom, Lv.c64.bh2, Lv.c32.adinv, const_cast<float*>(Lv.c32.sinv), s);
     for (int k = 0; k < 1; ++k) {
       launch_fill(Lv.x.u, 3 * (Lv.n_u + Lv.n_p), 0.0, s);
       launch_fill_f32(Lv.x32.u, 3 * (Lv.n_u + Lv.n_p), 0.0f, s);
@@ -1019,6 +1068,48 @@ int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
   Vec<float> x{u, p}, f{const_cast<float*>(fu), const_cast<float*>(gp)};
   top_cycle<float>(h, x, f, false, nullptr, (hipStream_t)sv);
   return launch_status("smg_cycle_f32");
+}
+
+int smg_error_norm(smg_t h, const double* u, const double* p, const double* us, const double* ps, double* out,
+                   smg_stream_t sv) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  if (!u || !p || !us || !ps || !out) return fail(SMG_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)sv;
+  Level& T = h->lv[h->L];
+  double ah[4];
+  for (int k = 0; k < 4; ++k) ah[k] = 1.0 / T.c64.adinv[k];
+  launch_error_norm(T.N, h->dom, T.c64.bh2, ah, T.c64.sinv, u, p, us, ps, h->red, h->enorm, s);
+  double v[4];
+  HIPCHK(hipMemcpyAsync(v, h->enorm, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *out = std::sqrt(std::max(v[2] + v[3], 0.0));
+  return SMG_OK;
+}
+
+int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* us, const double* ps, double eps,
+                    int maxit, double* u, double* p, int* iters, double* rate, smg_stream_t sv) {
+  if (!h) return fail(SMG_EINVAL, "null handle");
+  if (!fu || !gp || !us || !ps || !u || !p) return fail(SMG_EINVAL, "null vector");
+  if (!(eps > 0) || maxit < 1) return fail(SMG_EINVAL, "eps must be > 0 and maxit >= 1");
+  double e0 = 0.0, e = 0.0;
+  int rc = smg_error_norm(h, u, p, us, ps, &e0, sv);
+  if (rc) return rc;
+  if (iters) *iters = 0;
+  if (rate) *rate = 0.0;
+  if (e0 == 0.0) return SMG_OK;
+  for (int n = 1; n <= maxit; ++n) {
+    if ((rc = smg_cycle(h, fu, gp, u, p, sv)) != SMG_OK) return rc;
+    if ((rc = smg_error_norm(h, u, p, us, ps, &e, sv)) != SMG_OK) return rc;
+    if (iters) *iters = n;
+    if (!std::isfinite(e)) {
+      if (rate) *rate = INFINITY;
+      return SMG_ENONFINITE;
+    }
+    if (rate) *rate = std::pow(e / e0, 1.0 / n);
+    if (e > 1e6 * e0) return SMG_DIVERGED;
+    if (e <= eps * e0) return SMG_OK;
+  }
+  return SMG_NOCONV;
 }
 
 int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxit, double* u,

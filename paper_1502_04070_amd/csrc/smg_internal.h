@@ -45,11 +45,22 @@ __device__ __forceinline__ J block_job(const JobArg<J>& A, int b, int& tile) {
 // Domains on the grid of N x N squares (lattice point (a, b) at
 // (a / 2N, b / 2N), vertex (i, j) at (i / N, j / N)):
 //   0: the unit square;
-//   1: the L-shape, the unit square without [1/2, 1]^2 (N even).
+//   1: the L-shape, the unit square without [1/2, 1]^2 (N even);
+//   2: the unit square on the union-jack grid (N even): the squares of the
+//      lower-left and upper-right quarters are cut by the diagonal from their
+//      lower-left to their upper-right corner, the others by the other
+//      diagonal, so that the diagonals of the coarsest 2 x 2 grid meet at the
+//      centre.
 // dom_u: the lattice point carries velocity unknowns (inside, off the boundary);
 // dom_p: the vertex belongs to the closed domain (pressure node);
 // dom_sq: the square belongs to the domain.
-enum { SMG_DOM_SQUARE = 0, SMG_DOM_LSHAPE = 1 };
+enum { SMG_DOM_SQUARE = 0, SMG_DOM_LSHAPE = 1, SMG_DOM_UNIONJACK = 2 };
+
+// diagonal of square (si, sj) on the union-jack grid: 0 from the lower-left to
+// the upper-right corner, 1 from the upper-left to the lower-right corner
+__host__ __device__ inline int uj_orient(int N, int si, int sj) {
+  return ((2 * si < N) != (2 * sj < N)) ? 1 : 0;
+}
 
 __host__ __device__ inline bool dom_u(int N, int dom, int a, int b) {
   return a > 0 && a < 2 * N && b > 0 && b < 2 * N && !(dom == SMG_DOM_LSHAPE && a >= N && b >= N);
@@ -61,10 +72,17 @@ __host__ __device__ inline bool dom_sq(int N, int dom, int si, int sj) {
   return si >= 0 && si < N && sj >= 0 && sj < N && !(dom == SMG_DOM_LSHAPE && 2 * si >= N && 2 * sj >= N);
 }
 // int phi_i / h^2 of the P1 basis function of vertex (i, j): (h^2 / 6) times
-// the number of triangles of the domain around it (the same-diagonal grid
-// has two triangles of square (i-1, j-1) and of square (i, j) at the vertex,
-// one of square (i, j-1) and one of square (i-1, j))
+// the number of triangles of the domain around it (a square cut from its
+// lower-left to its upper-right corner has two triangles at those corners
+// and one at the other two; the other diagonal the reverse)
 __host__ __device__ inline double p1_count_w(int N, int dom, int i, int j) {
+  if (dom == SMG_DOM_UNIONJACK) {
+    auto two = [&](int si, int sj, bool main_corner) {
+      if (!dom_sq(N, dom, si, sj)) return 0;
+      return (uj_orient(N, si, sj) == 0) == main_corner ? 2 : 1;
+    };
+    return (two(i - 1, j - 1, true) + two(i, j - 1, false) + two(i - 1, j, false) + two(i, j, true)) / 6.0;
+  }
   const int c = 2 * dom_sq(N, dom, i - 1, j - 1) + dom_sq(N, dom, i, j - 1) + dom_sq(N, dom, i - 1, j) +
                 2 * dom_sq(N, dom, i, j);
   return c / 6.0;
@@ -79,6 +97,7 @@ struct LevelCoef {
   T acoef[4][5];     // A = K + beta h^2 M, grouped lattice taps per node class
   T adinv[4];        // 1 / Ahat per node class (V, H, E, D)
   T h;               // 1 / N (scales B and B^T)
+  T bh2;             // beta h^2 (scales the mass part of A)
   const T* sinv;     // 1 / Shat at every pressure node, (N+1)^2
 };
 
@@ -172,7 +191,7 @@ void launch_project_dual(int N, int dom, double* p, double* partials, hipStream_
 
 // Shat^-1 at setup
 template <class T>
-void launch_shat_inv(int N, int dom, const T* adinv_host4, T* sinv, hipStream_t s);
+void launch_shat_inv(int N, int dom, double bh2, const T* adinv_host4, T* sinv, hipStream_t s);
 
 // load vectors / masses
 // mode 0: interior rows from interior values; 1: all rows from interior values;
@@ -188,6 +207,12 @@ void launch_dot(int N, int dom, int which, const double* a, const double* b, dou
                 double* out, hipStream_t s);
 // out[0] = sum of np partials (fixed order)
 void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
+// Section 6 error measure pieces of (u, p) - (us, ps); scratch of
+// enorm_scratch(N) doubles, out: 4 doubles (see the kernels)
+int enorm_scratch(int N);
+void launch_error_norm(int N, int dom, double bh2, const double* ahat4, const double* sinv, const double* u,
+                       const double* p, const double* us, const double* ps, double* red, double* out,
+                       hipStream_t s);
 
 // Convergence bookkeeping of the solve loop (device-side).
 struct SolveState {

@@ -12,10 +12,13 @@
 // thread per square, TX x TY squares per workgroup, the input window with a
 // halo of one square staged in LDS.  All operators are HBM-bound (about 2-4
 // flop per byte); no matrix core work is involved.
+#include <algorithm>
+
 #include "smg_internal.h"
 
 namespace smg {
 #include "stencils.inc"
+#include "smg_uj.h"
 using namespace smg_stencil;
 
 // ---------------------------------------------------------------------------
@@ -124,13 +127,28 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
   const bool hp = FL::on(F_IN_P, J.in_p);
   auto C = [&](int g) -> T { return J.L.acoef[CLS][g]; };
   auto P = [&](int di, int dj) -> T { return sp[ty + 1 + dj][tx + 1 + di]; };
-  const T dscale = FL::on_int(F_DIAG_U, J.diag_u) ? J.L.adinv[CLS] : T(1);
+  T dscale = FL::on_int(F_DIAG_U, J.diag_u) ? J.L.adinv[CLS] : T(1);
+  // union-jack grid: the rows summed over the squares at the node, and the
+  // diagonal of A with them
+  T yuj[2] = {T(0), T(0)};
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    auto Us = [&](int c, int da, int db) -> T { return su[c][2 * ty + 2 + db][2 * tx + 2 + da]; };
+    auto Ps = [&](int di, int dj) -> T { return sp[ty + 1 + dj][tx + 1 + di]; };
+    auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+    T dg;
+    uj_vel_rows<CLS, T>(J.L.bh2, J.L.h, hu, hp, Us, Ps, OR, yuj[0], yuj[1], dg);
+    if (FL::on_int(F_DIAG_U, J.diag_u)) dscale = T(1) / dg;
+  }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     auto U = [&](int da, int db) -> T { return su[c][lb + db][la + da]; };
     T y = T(0);
-    if (hu) y += a_row<CLS, T>(U, C);
-    if (hp) y += J.L.h * (c == 0 ? btx_row<CLS, T>(P) : bty_row<CLS, T>(P));
+    if constexpr (DOM == SMG_DOM_UNIONJACK) {
+      y = yuj[c];
+    } else {
+      if (hu) y += a_row<CLS, T>(U, C);
+      if (hp) y += J.L.h * (c == 0 ? btx_row<CLS, T>(P) : bty_row<CLS, T>(P));
+    }
     const size_t g = (size_t)c * M * M + (size_t)b * M + a;
     const T r = (FL::on(F_RHS_U, J.rhs_u) ? J.rhs_u[g] : T(0)) - y;
     if (FL::on(F_PARTIAL, J.partial) && interior) nrm += (double)r * (double)r;
@@ -198,7 +216,14 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       const int la = 2 * tx + 2, lb = 2 * ty + 2;
       auto U0 = [&](int da, int db) -> T { return su[0][lb + db][la + da]; };
       auto U1 = [&](int da, int db) -> T { return su[1][lb + db][la + da]; };
-      const T y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
+      T y;
+      if constexpr (DOM == SMG_DOM_UNIONJACK) {
+        auto Us = [&](int c, int da, int db) -> T { return su[c][lb + db][la + da]; };
+        auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+        y = hu ? uj_p_row<T>(J.L.h, Us, OR) : T(0);
+      } else {
+        y = hu ? J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1)) : T(0);
+      }
       const size_t g = (size_t)j * NP + i;
       // vertices outside the domain carry no pressure unknown: zero row
       const bool pin = dom_p(N, dom, i, j);
@@ -298,9 +323,24 @@ unsigned stencil_flags(const StencilJob<T>& J, int rows) {
   return f;
 }
 
+// union-jack grid: the generic kernel (flags read from the job) with the rows
+// summed square by square
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_stencil_uj(StencilJob<T> J) {
+  if (J.done && *J.done) return;
+  stencil_tile<T, TX, TY, 0u, SMG_DOM_UNIONJACK>(J, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
 template <class T, int TX, int TY>
 static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s) {
   const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
+  if (J.L.dom == SMG_DOM_UNIONJACK) {
+    StencilJob<T> G = J;
+    if (!(rows & ROWS_U)) { G.out_u = nullptr; }
+    if (!(rows & ROWS_P)) { G.out_p = nullptr; }
+    k_stencil_uj<T, TX, TY><<<nb, TX * TY, 0, s>>>(G);
+    return;
+  }
   const unsigned f = job_flags(J, rows);
 #define SMG_CASE(MODE) \
   case MODE: k_stencil<T, TX, TY, MODE><<<nb, TX * TY, 0, s>>>(J); return;
@@ -426,11 +466,70 @@ __global__ __launch_bounds__(256) void k_restrict(int Nc, int dom, const T* __re
   if (xcp) xcp[(size_t)J * (Nc + 1) + I] = T(0);
 }
 
+// Union-jack grid: the transpose of the prolongation gathered square by
+// square.  Every fine point is owned by one coarse square (the lower-left
+// closed, upper-right open part of it; squares I = Nc or J = Nc own the right
+// and top boundary), and its prolongation weights involve only that square's
+// coarse nodes, so the coarse node (A, B) collects from the squares that
+// contain it the owned fine points weighted by its column of the square's
+// prolongation table.
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict_uj(int Nc, const T* __restrict__ rfu,
+                                                     const T* __restrict__ rfp, T* rcu, T* rcp,
+                                                     T* xcu, T* xcp, const int* done) {
+  using namespace smg_stencil;
+  if (done && *done) return;
+  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (I > Nc || J > Nc) return;
+  const int Nf = 2 * Nc, Mc = 2 * Nc + 1, Mf = 2 * Nf + 1, NPf = Nf + 1;
+  for (int cls = 0; cls < 4; ++cls) {
+    const int CA = cls & 1, CB = cls >> 1, A = 2 * I + CA, B = 2 * J + CB;
+    if (A > 2 * Nc || B > 2 * Nc) continue;
+    const bool interior = dom_u(Nc, SMG_DOM_UNIONJACK, A, B);
+    T v[2] = {T(0), T(0)};
+    for (int dj = (CB ? 0 : -1); dj <= 0; ++dj)
+      for (int di = (CA ? 0 : -1); di <= 0; ++di) {
+        const int SI = I + di, SJ = J + dj;
+        if (SI < 0 || SJ < 0) continue;
+        const int o = uj_orient_c(Nc, SI, SJ), cl = 3 * (CB - 2 * dj) + (CA - 2 * di);
+        for (int f = 0; f < 16; ++f) {
+          const double w = UJ_PRO[o][f][cl];
+          const int a = 4 * SI + (f & 3), b = 4 * SJ + (f >> 2);
+          if (w == 0.0 || !dom_u(Nf, SMG_DOM_UNIONJACK, a, b)) continue;
+          v[0] += T(w) * rfu[(size_t)b * Mf + a];
+          v[1] += T(w) * rfu[(size_t)Mf * Mf + (size_t)b * Mf + a];
+        }
+      }
+    for (int c = 0; c < 2; ++c) {
+      const size_t g = (size_t)c * Mc * Mc + (size_t)B * Mc + A;
+      rcu[g] = interior ? v[c] : T(0);
+      if (xcu) xcu[g] = T(0);
+    }
+  }
+  T vp = T(0);
+  for (int dj = -1; dj <= 0; ++dj)
+    for (int di = -1; di <= 0; ++di) {
+      const int SI = I + di, SJ = J + dj;
+      if (SI < 0 || SJ < 0) continue;
+      const int o = uj_orient_c(Nc, SI, SJ), q = 2 * (-dj) + (-di);
+      for (int v = 0; v < 4; ++v) {
+        const double w = UJ_PP[o][v][q];
+        const int fi = 2 * SI + (v & 1), fj = 2 * SJ + (v >> 1);
+        if (w == 0.0 || fi > Nf || fj > Nf) continue;
+        vp += T(w) * rfp[(size_t)fj * NPf + fi];
+      }
+    }
+  rcp[(size_t)J * (Nc + 1) + I] = vp;
+  if (xcp) xcp[(size_t)J * (Nc + 1) + I] = T(0);
+}
+
 template <class T>
 void launch_restrict(int Nc, int dom, const T* rfu, const T* rfp, T* rcu, T* rcp, T* xcu, T* xcp,
                      const int* done, hipStream_t s) {
   dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
-  k_restrict<T><<<grid, 256, 0, s>>>(Nc, dom, rfu, rfp, rcu, rcp, xcu, xcp, done);
+  if (dom == SMG_DOM_UNIONJACK) k_restrict_uj<T><<<grid, 256, 0, s>>>(Nc, rfu, rfp, rcu, rcp, xcu, xcp, done);
+  else k_restrict<T><<<grid, 256, 0, s>>>(Nc, dom, rfu, rfp, rcu, rcp, xcu, xcp, done);
 }
 template void launch_restrict<double>(int, int, const double*, const double*, double*, double*,
                                       double*, double*, const int*, hipStream_t);
@@ -527,11 +626,53 @@ void launch_prolong_b(const JobArg<ProJob<T>>& A, int nb, hipStream_t s) {
 template void launch_prolong_b<double>(const JobArg<ProJob<double>>&, int, hipStream_t);
 template void launch_prolong_b<float>(const JobArg<ProJob<float>>&, int, hipStream_t);
 
+// Union-jack grid: every coarse square adds the interpolant of its coarse
+// nodes at the fine points it owns, with the table of its diagonal direction.
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_uj(int Nc, const T* __restrict__ zu,
+                                                    const T* __restrict__ zp, T* u, T* p,
+                                                    const int* done) {
+  using namespace smg_stencil;
+  if (done && *done) return;
+  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (I > Nc || J > Nc) return;
+  const int Nf = 2 * Nc, Mc = 2 * Nc + 1, Mf = 2 * Nf + 1, NPc = Nc + 1, NPf = Nf + 1;
+  const int o = uj_orient_c(Nc, I, J);
+  for (int c = 0; c < 2; ++c) {
+    T z[9];
+    for (int k = 0; k < 9; ++k) {
+      const int A = 2 * I + k % 3, B = 2 * J + k / 3;
+      z[k] = dom_u(Nc, SMG_DOM_UNIONJACK, A, B) ? zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
+    }
+    for (int f = 0; f < 16; ++f) {
+      const int a = 4 * I + (f & 3), b = 4 * J + (f >> 2);
+      if (!dom_u(Nf, SMG_DOM_UNIONJACK, a, b)) continue;
+      T v = T(0);
+      for (int k = 0; k < 9; ++k) v += T(UJ_PRO[o][f][k]) * z[k];
+      u[(size_t)c * Mf * Mf + (size_t)b * Mf + a] += v;
+    }
+  }
+  T zc[4];
+  for (int q = 0; q < 4; ++q) {
+    const int ci = I + (q & 1), cj = J + (q >> 1);
+    zc[q] = (ci <= Nc && cj <= Nc) ? zp[(size_t)cj * NPc + ci] : T(0);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int fi = 2 * I + (v & 1), fj = 2 * J + (v >> 1);
+    if (fi > Nf || fj > Nf) continue;
+    T w = T(0);
+    for (int q = 0; q < 4; ++q) w += T(UJ_PP[o][v][q]) * zc[q];
+    p[(size_t)fj * NPf + fi] += w;
+  }
+}
+
 template <class T>
 void launch_prolong_add(int Nc, int dom, const T* zu, const T* zp, T* u, T* p, const int* done,
                         hipStream_t s) {
   dim3 grid((Nc + 16) / 16, (Nc + 16) / 16);
-  k_prolong_add<T><<<grid, 256, 0, s>>>(Nc, dom, zu, zp, u, p, done);
+  if (dom == SMG_DOM_UNIONJACK) k_prolong_uj<T><<<grid, 256, 0, s>>>(Nc, zu, zp, u, p, done);
+  else k_prolong_add<T><<<grid, 256, 0, s>>>(Nc, dom, zu, zp, u, p, done);
 }
 template void launch_prolong_add<double>(int, int, const double*, const double*, double*, double*,
                                          const int*, hipStream_t);
@@ -686,13 +827,44 @@ __global__ __launch_bounds__(256) void k_shat_inv(int N, int dom, T ad0, T ad1, 
   sinv[e] = dom_p(N, dom, i, j) ? T(1) / S : T(0);
 }
 
+// Union-jack grid: the B row of vertex (i, j) assembled from the four squares
+// around it on the 5 x 5 lattice window centred at the vertex, then
+// Shat = h^2 sum over interior nodes of (Bx^2 + By^2) / Ahat (Ahat per node).
 template <class T>
-void launch_shat_inv(int N, int dom, const T* ad, T* sinv, hipStream_t s) {
-  const int n = (N + 1) * (N + 1);
-  k_shat_inv<T><<<(n + 255) / 256, 256, 0, s>>>(N, dom, ad[0], ad[1], ad[2], ad[3], sinv);
+__global__ __launch_bounds__(256) void k_shat_inv_uj(int N, double bh2, T* sinv) {
+  using namespace smg_stencil;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1);
+  double bx[25], by[25];
+  for (int k = 0; k < 25; ++k) bx[k] = by[k] = 0.0;
+  for (int dj = -1; dj <= 0; ++dj)
+    for (int di = -1; di <= 0; ++di) {
+      if (!dom_sq(N, SMG_DOM_UNIONJACK, i + di, j + dj)) continue;
+      const int o = uj_orient(N, i + di, j + dj), q = 2 * (-dj) + (-di);
+      for (int m = 0; m < 9; ++m) {
+        const int w = (2 * dj + m / 3 + 2) * 5 + (2 * di + m % 3 + 2);
+        bx[w] += UJ_BX[o][q][m];
+        by[w] += UJ_BY[o][q][m];
+      }
+    }
+  double S = 0.0;
+  for (int w = 0; w < 25; ++w) {
+    const int a = 2 * i + w % 5 - 2, b = 2 * j + w / 5 - 2;
+    if (!dom_u(N, SMG_DOM_UNIONJACK, a, b) || (bx[w] == 0.0 && by[w] == 0.0)) continue;
+    S += (bx[w] * bx[w] + by[w] * by[w]) / uj_adiag(N, a, b, bh2);
+  }
+  sinv[e] = T(1.0 / (S / ((double)N * (double)N)));
 }
-template void launch_shat_inv<double>(int, int, const double*, double*, hipStream_t);
-template void launch_shat_inv<float>(int, int, const float*, float*, hipStream_t);
+
+template <class T>
+void launch_shat_inv(int N, int dom, double bh2, const T* ad, T* sinv, hipStream_t s) {
+  const int n = (N + 1) * (N + 1);
+  if (dom == SMG_DOM_UNIONJACK) k_shat_inv_uj<T><<<(n + 255) / 256, 256, 0, s>>>(N, bh2, sinv);
+  else k_shat_inv<T><<<(n + 255) / 256, 256, 0, s>>>(N, dom, ad[0], ad[1], ad[2], ad[3], sinv);
+}
+template void launch_shat_inv<double>(int, int, double, const double*, double*, hipStream_t);
+template void launch_shat_inv<float>(int, int, double, const float*, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // masses (load vectors and the adjoint): one thread per square, direct loads
@@ -735,15 +907,44 @@ __global__ __launch_bounds__(256) void k_mass_u(int N, int dom, int rows_all, in
   mass_node<3>(N, dom, i, j, rows_all, read_all, u, y, scale, acc);
 }
 
+// union-jack grid: P2 mass rows summed square by square (squares of the grid only)
+__global__ __launch_bounds__(256) void k_mass_u_uj(int N, int rows_all, int read_all,
+                                                   const double* __restrict__ u, double* y, double scale,
+                                                   int acc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1), M = 2 * N + 1;
+  const double h2 = 1.0 / ((double)N * (double)N);
+  for (int cls = 0; cls < 4; ++cls) {
+    const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+    if (a > 2 * N || b > 2 * N) continue;
+    const bool interior = dom_u(N, SMG_DOM_UNIONJACK, a, b);
+    for (int c = 0; c < 2; ++c) {
+      const double* uc = u + (size_t)c * M * M;
+      auto U = [&](int la, int lb) -> double {
+        const int aa = 2 * i + la, bb = 2 * j + lb;
+        const bool ok = read_all ? (aa >= 0 && aa <= 2 * N && bb >= 0 && bb <= 2 * N)
+                                 : dom_u(N, SMG_DOM_UNIONJACK, aa, bb);
+        return ok ? uc[(size_t)bb * M + aa] : 0.0;
+      };
+      const double v = (interior || rows_all) ? h2 * uj_m_row<double>(N, a, b, U) : 0.0;
+      const size_t g = (size_t)c * M * M + (size_t)b * M + a;
+      y[g] = acc ? y[g] + scale * v : v;
+    }
+  }
+}
+
 void launch_mass_u(int N, int dom, int mode, const double* u, double* y, hipStream_t s) {
   // mode 0: rows interior, read interior; 1: rows all, read interior; 2: rows interior, read all
   const int n = (N + 1) * (N + 1);
-  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, 1.0, 0);
+  if (dom == SMG_DOM_UNIONJACK) k_mass_u_uj<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, 1.0, 0);
+  else k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, 1.0, 0);
 }
 
 void launch_mass_u_acc(int N, int dom, int mode, const double* u, double scale, double* y, hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, scale, 1);
+  if (dom == SMG_DOM_UNIONJACK) k_mass_u_uj<<<(n + 255) / 256, 256, 0, s>>>(N, mode == 1, mode == 2, u, y, scale, 1);
+  else k_mass_u<<<(n + 255) / 256, 256, 0, s>>>(N, dom, mode == 1, mode == 2, u, y, scale, 1);
 }
 
 // P1 mass: the six triangles around vertex (i, j) of the same-diagonal grid,
@@ -769,9 +970,21 @@ __global__ __launch_bounds__(256) void k_mass_p(int N, int dom, const double* __
   gp[e] = s / (24.0 * (double)N * (double)N);
 }
 
+__global__ __launch_bounds__(256) void k_mass_p_uj(int N, const double* __restrict__ g, double* gp) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const int i = e % (N + 1), j = e / (N + 1), NP = N + 1;
+  auto G = [&](int di, int dj) -> double {
+    const int ii = i + di, jj = j + dj;
+    return (ii >= 0 && ii <= N && jj >= 0 && jj <= N) ? g[(size_t)jj * NP + ii] : 0.0;
+  };
+  gp[e] = uj_mp_row<double>(N, i, j, G) / ((double)N * (double)N);
+}
+
 void launch_mass_p(int N, int dom, const double* g, double* gp, hipStream_t s) {
   const int n = (N + 1) * (N + 1);
-  k_mass_p<<<(n + 255) / 256, 256, 0, s>>>(N, dom, g, gp);
+  if (dom == SMG_DOM_UNIONJACK) k_mass_p_uj<<<(n + 255) / 256, 256, 0, s>>>(N, g, gp);
+  else k_mass_p<<<(n + 255) / 256, 256, 0, s>>>(N, dom, g, gp);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,6 +1031,84 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
 
 void launch_reduce(const double* partials, int np, double* out, hipStream_t s) {
   k_reduce_final<<<1, 256, 0, s>>>(partials, np, out);
+}
+
+// ---------------------------------------------------------------------------
+// error measure of the experiments (Section 6): ||(u, p) - (us, ps)||_L with
+// L = diag(Ahat, Shat), the pressure difference made mean-free first
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double enorm_ahat(int N, int dom, double bh2, const double* ad, int a, int b) {
+  if (dom == SMG_DOM_UNIONJACK) return uj_adiag(N, a, b, bh2);
+  return ad[(a & 1) + 2 * (b & 1)];
+}
+
+// mode 0: partials of sum w d and sum w (d = p - ps, w = P1 weights), in two
+// arrays of nb entries; mode 1: partials of sum Shat (d - mean)^2, the mean
+// read from sums[0] / sums[1]
+__global__ __launch_bounds__(256) void k_enorm_p(int N, int dom, int mode, const double* __restrict__ p,
+                                                 const double* __restrict__ ps, const double* __restrict__ sinv,
+                                                 const double* __restrict__ sums, double* partials, int nb) {
+  __shared__ double red[4];
+  const int n = (N + 1) * (N + 1);
+  const double mean = mode == 1 ? sums[0] / sums[1] : 0.0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int e = blockIdx.x * 1024 + k * 256 + threadIdx.x;
+    if (e >= n || !dom_p(N, dom, e % (N + 1), e / (N + 1))) continue;
+    const double d = p[e] - ps[e];
+    if (mode == 0) {
+      const double w = p1_count_w(N, dom, e % (N + 1), e / (N + 1));
+      s1 += w * d;
+      s2 += w;
+    } else if (sinv[e] != 0.0) {
+      s1 += (d - mean) * (d - mean) / sinv[e];
+    }
+  }
+  const double t1 = block_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = block_sum<256>(s2, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = t1;
+    if (mode == 0) partials[nb + blockIdx.x] = t2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_enorm_u(int N, int dom, double bh2, double a0, double a1, double a2,
+                                                 double a3, const double* __restrict__ u,
+                                                 const double* __restrict__ us, double* partials) {
+  __shared__ double red[4];
+  const int M = 2 * N + 1;
+  const int64_t n = 2LL * M * M;
+  const double ad[4] = {a0, a1, a2, a3};
+  double s = 0.0;
+  for (int k = 0; k < DOT_PER_THREAD; ++k) {
+    const int64_t e = (int64_t)blockIdx.x * 256 * DOT_PER_THREAD + k * 256 + threadIdx.x;
+    if (e >= n) continue;
+    const int q = (int)(e % ((int64_t)M * M)), a = q % M, b = q / M;
+    if (!dom_u(N, dom, a, b)) continue;
+    const double d = u[e] - us[e];
+    s += enorm_ahat(N, dom, bh2, ad, a, b) * d * d;
+  }
+  const double t = block_sum<256>(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+int enorm_scratch(int N) { return std::max(dot_blocks(N, 0), 2 * ((N + 1) * (N + 1) + 1023) / 1024 + 2); }
+
+// out[0..1]: mean pieces, out[2]: pressure part, out[3]: velocity part
+void launch_error_norm(int N, int dom, double bh2, const double* ahat4, const double* sinv, const double* u,
+                       const double* p, const double* us, const double* ps, double* red, double* out,
+                       hipStream_t s) {
+  const int nbp = ((N + 1) * (N + 1) + 1023) / 1024;
+  k_enorm_p<<<nbp, 256, 0, s>>>(N, dom, 0, p, ps, sinv, nullptr, red, nbp);
+  k_reduce_final<<<1, 256, 0, s>>>(red, nbp, out);
+  k_reduce_final<<<1, 256, 0, s>>>(red + nbp, nbp, out + 1);
+  k_enorm_p<<<nbp, 256, 0, s>>>(N, dom, 1, p, ps, sinv, out, red, nbp);
+  k_reduce_final<<<1, 256, 0, s>>>(red, nbp, out + 2);
+  const int nbu = dot_blocks(N, 0);
+  k_enorm_u<<<nbu, 256, 0, s>>>(N, dom, bh2, ahat4[0], ahat4[1], ahat4[2], ahat4[3], u, us, red);
+  k_reduce_final<<<1, 256, 0, s>>>(red, nbu, out + 3);
 }
 
 void launch_dot(int N, int dom, int which, const double* a, const double* b, double* partials,

@@ -48,9 +48,11 @@ def _apply_damping(set_level, damping):
 
 def _set_domain(params, domain):
     """"square": the unit square; "l_shape": the unit square without
-    [1/2, 1]^2 (needs an even n0).  The lattice layouts are those of the
-    square; entries at points outside the domain are ignored and written zero
-    or left as they were."""
+    [1/2, 1]^2 (needs an even n0); "union_jack": the unit square on the grid
+    of the paper's experiments, the diagonals of the coarsest 2 x 2 grid
+    meeting at the centre (even n0, unfused kernels, no batches).  The lattice
+    layouts are those of the square; entries at points outside the domain are
+    ignored and written zero or left as they were."""
     if domain not in _lib.DOMAINS:
         raise ValueError(f"domain must be one of {list(_lib.DOMAINS)}")
     params.domain = _lib.DOMAINS[domain]
@@ -307,6 +309,29 @@ class Hierarchy:
                                           _ptr(u), _ptr(p), C.byref(it), C.byref(rel), _stream())
         _lib.check(code, "smg_implicit_step", soft_ok=True)
         return SolveInfo(_lib.STATUS[code], it.value, rel.value, [])
+
+    def error_norm(self, u, p, us, ps) -> float:
+        """||(u, p) - (us, ps)||_L of Section 6 (pressure difference made mean-free)."""
+        L = self.L
+        self._chk(L, (u, "u"), (p, "p"), (us, "u"), (ps, "p"))
+        out = C.c_double()
+        _lib.check(self.lib.smg_error_norm(self.h, _ptr(u), _ptr(p), _ptr(us), _ptr(ps), C.byref(out), _stream()),
+                   "smg_error_norm")
+        return out.value
+
+    def solve_error(self, fu, gp, us, ps, eps=1e-9, maxit=200, u=None, p=None):
+        """The protocol of Section 6: iterate from (u, p) (zero by default) on
+        (fu, gp) until the L-norm error to x* = (us, ps) has dropped by eps.
+        Returns (u, p, iters, rate, status)."""
+        L = self.L
+        if u is None:
+            u, p = self.zeros()
+        self._chk(L, (fu, "u"), (gp, "p"), (us, "u"), (ps, "p"), (u, "u"), (p, "p"))
+        it, rate = C.c_int(), C.c_double()
+        code = self.lib.smg_solve_error(self.h, _ptr(fu), _ptr(gp), _ptr(us), _ptr(ps), float(eps), int(maxit),
+                                        _ptr(u), _ptr(p), C.byref(it), C.byref(rate), _stream())
+        _lib.check(code, "smg_solve_error", soft_ok=True)
+        return u, p, it.value, rate.value, _lib.STATUS[code]
 
     def solve_mixed(self, fu, gp, rtol=1e-10, maxit=400, u=None, p=None):
         """FP32 cycles inside FP64 iterative refinement."""

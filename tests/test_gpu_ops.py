@@ -119,7 +119,7 @@ def test_transfers_match_oracle(Nc, n0):
     assert relmax(lat.from_lattice(df, host(U), host(Pp)), ref) <= TOL
 
 
-@pytest.mark.parametrize("n0,beta", [(2, 0.0), (2, 1.0), (4, 1e4), (4, 1e6), (3, 10.0)])
+@pytest.mark.parametrize("n0,beta", [(2, 0.0), (2, 1.0), (4, 1e4), (4, 1e6), (3, 10.0), (2, 1e10)])
 def test_coarse_solve_matches_direct(n0, beta):
     oh = oracle_level(n0, beta, n0)
     gh = gpu_hier(n0, beta, n0=n0)
