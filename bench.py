@@ -305,6 +305,32 @@ def extras():
             del hh
         rec[f"beta={beta:g}"] = r
     out["l_shape_h256"] = rec
+    torch.cuda.empty_cache()
+
+    # the measurement protocol of Section 6 on the union-jack grid (Tables 2
+    # and 3): NE and Uzawa W(3,3), levels k = 4..8 (h = 1/32 .. 1/512), six
+    # beta, x* = nodal values of the Section 6 fields (the paper projects
+    # them in L2), f = calA x*, stop when the L-norm error dropped by 1e-9
+    betas6 = [0.0, 1e2, 1e4, 1e6, 1e8, 1e10]
+    rec = {"x_star": "nodal interpolant of u = phi (y - 1/2, 1/2 - x), p = phi", "eps": 1e-9,
+           "cycle": "W(3,3)", "betas": betas6}
+    for k in range(4, 9):
+        N = 2 ** (k + 1)
+        us, ps = inputs.section6_fields(N)
+        Us, Ps = torch.from_numpy(us).cuda(), torch.from_numpy(ps).cuda()
+        lev = {}
+        for name, sm in (("ne", "ne"), ("uzawa", "uzawa")):
+            runs, t_all = [], 0.0
+            for beta in betas6:
+                hh = Hierarchy(N, beta, smoother=sm, nu_pre=3, nu_post=3, gamma=2, domain="union_jack")
+                FU, GP = hh.apply(Us, Ps)
+                (_, _, n, q, st), t_s = _timed(lambda: hh.solve_error(FU, GP, Us, Ps, eps=1e-9, maxit=200))
+                runs.append([n if st == "ok" else None, round(q, 3)])
+                t_all += t_s
+                del hh
+            lev[name] = {"iterations_rate": runs, "ms_per_iterate": 1e3 * t_all / max(1, sum(r[0] or 0 for r in runs))}
+        rec[f"k={k}"] = lev
+    out["paper_protocol_union_jack"] = rec
     return out
 
 

@@ -105,6 +105,8 @@ struct smg_hier {
   double* enorm = nullptr;         // 4 doubles (error-measure pieces)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
+  hipGraphExec_t gerr = nullptr;   // protocol iterate (cycle, projection, error measure)
+  const void* gerr_key[6] = {};    // the vectors it was captured with
   // single-workgroup iterate of levels 0..Lc (Lc = -1: not used)
   int Lc = -1;
   int* cc_ops = nullptr;
@@ -128,6 +130,7 @@ struct smg_hier {
     // teardown: errors cannot be reported from a destructor
     if (g64) (void)hipGraphExecDestroy(g64);
     if (g32) (void)hipGraphExecDestroy(g32);
+    if (gerr) (void)hipGraphExecDestroy(gerr);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -382,10 +385,19 @@ void fill_vec(Level& L, Vec<T> v, hipStream_t s) {
 
 // Multigrid iterate of Section 3 on level l for (x, f); zg: x = 0 on entry.
 template <class T>
+void coarse_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s);
+
+template <class T>
 void cycle_rec(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
   Level& L = H->lv[l];
   if (l == 0) {
     launch_coarse_solve<T>(L.N, H->dom, H->nc, H->cinv, f.u, f.p, x.u, x.p, done, s);
+    return;
+  }
+  // the union-jack grid (always on this path) does its coarse levels in the
+  // single-workgroup kernel: a W-cycle visits them thousands of times
+  if (H->dom == SMG_DOM_UNIONJACK && l <= H->Lc) {
+    coarse_cycle<T>(H, x, f, zg, done, s);
     return;
   }
   const smg_params& prm = H->prm;
@@ -1070,15 +1082,47 @@ int smg_cycle_f32(smg_t h, const float* fu, const float* gp, float* u, float* p,
   return launch_status("smg_cycle_f32");
 }
 
+static void enqueue_error_norm(smg_hier* h, const double* u, const double* p, const double* us, const double* ps,
+                               hipStream_t s) {
+  Level& T = h->lv[h->L];
+  double ah[4];
+  for (int k = 0; k < 4; ++k) ah[k] = 1.0 / T.c64.adinv[k];
+  launch_error_norm(T.N, h->dom, T.c64.bh2, ah, T.c64.sinv, u, p, us, ps, h->red, h->enorm, s);
+}
+
+// One iterate of the protocol, its projection and the error measure, as one
+// graph (a W-cycle on the unfused path is thousands of launches); captured
+// once per set of vectors.
+static int protocol_graph(smg_hier* H, const double* fu, const double* gp, const double* us, const double* ps,
+                          double* u, double* p) {
+  const void* key[6] = {fu, gp, us, ps, u, p};
+  if (H->gerr && std::equal(key, key + 6, H->gerr_key)) return SMG_OK;
+  if (H->gerr) (void)hipGraphExecDestroy(H->gerr);
+  H->gerr = nullptr;
+  hipGraph_t g = nullptr;
+  hipStream_t cs = H->cap_stream;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  Vec<double> x{u, p}, f{const_cast<double*>(fu), const_cast<double*>(gp)};
+  top_cycle<double>(H, x, f, false, nullptr, cs);
+  project_mean(H, H->L, p, nullptr, cs);
+  enqueue_error_norm(H, u, p, us, ps, cs);
+  HIPCHK(hipStreamEndCapture(cs, &g));
+  hipError_t e = hipGraphInstantiate(&H->gerr, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    H->gerr = nullptr;
+    return fail(SMG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  std::copy(key, key + 6, H->gerr_key);
+  return SMG_OK;
+}
+
 int smg_error_norm(smg_t h, const double* u, const double* p, const double* us, const double* ps, double* out,
                    smg_stream_t sv) {
   if (!h) return fail(SMG_EINVAL, "null handle");
   if (!u || !p || !us || !ps || !out) return fail(SMG_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)sv;
-  Level& T = h->lv[h->L];
-  double ah[4];
-  for (int k = 0; k < 4; ++k) ah[k] = 1.0 / T.c64.adinv[k];
-  launch_error_norm(T.N, h->dom, T.c64.bh2, ah, T.c64.sinv, u, p, us, ps, h->red, h->enorm, s);
+  enqueue_error_norm(h, u, p, us, ps, s);
   double v[4];
   HIPCHK(hipMemcpyAsync(v, h->enorm, sizeof(v), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1097,9 +1141,14 @@ int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* u
   if (iters) *iters = 0;
   if (rate) *rate = 0.0;
   if (e0 == 0.0) return SMG_OK;
+  if ((rc = protocol_graph(h, fu, gp, us, ps, u, p)) != SMG_OK) return rc;
+  hipStream_t s = (hipStream_t)sv;
+  double v[4];
   for (int n = 1; n <= maxit; ++n) {
-    if ((rc = smg_cycle(h, fu, gp, u, p, sv)) != SMG_OK) return rc;
-    if ((rc = smg_error_norm(h, u, p, us, ps, &e, sv)) != SMG_OK) return rc;
+    HIPCHK(hipGraphLaunch(h->gerr, s));
+    HIPCHK(hipMemcpyAsync(v, h->enorm, sizeof(v), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    e = std::sqrt(std::max(v[2] + v[3], 0.0));
     if (iters) *iters = n;
     if (!std::isfinite(e)) {
       if (rate) *rate = INFINITY;
@@ -1131,7 +1180,8 @@ int smg_set_damping(smg_t h, int level, double tau, double sigma) {
   // captured iterates carry the old values in their launch arguments
   if (h->g64) (void)hipGraphExecDestroy(h->g64);
   if (h->g32) (void)hipGraphExecDestroy(h->g32);
-  h->g64 = h->g32 = nullptr;
+  if (h->gerr) (void)hipGraphExecDestroy(h->gerr);
+  h->g64 = h->g32 = h->gerr = nullptr;
   return SMG_OK;
 }
 

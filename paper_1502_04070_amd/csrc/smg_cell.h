@@ -15,6 +15,7 @@
 
 namespace smg {
 #include "stencils.inc"
+#include "smg_uj.h"
 }
 
 namespace smg {

@@ -854,6 +854,7 @@ template <class T>
 int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s) {
   const size_t lds = coarse_cycle_lds(J.n0, J.Lc, sizeof(T));
   if (J.L[0].dom == SMG_DOM_LSHAPE) k_coarse_cycle<T, SMG_DOM_LSHAPE><<<1, CC_THREADS, lds, s>>>(J);
+  else if (J.L[0].dom == SMG_DOM_UNIONJACK) k_coarse_cycle<T, SMG_DOM_UNIONJACK><<<1, CC_THREADS, lds, s>>>(J);
   else k_coarse_cycle<T, SMG_DOM_SQUARE><<<1, CC_THREADS, lds, s>>>(J);
   return 0;
 }
@@ -862,10 +863,11 @@ template int launch_coarse_cycle<float>(const CoarseJob<float>&, hipStream_t);
 
 template <class T>
 int coarse_cycle_allow_lds(size_t bytes) {
-  const void* fns[4] = {(const void*)k_coarse_cycle<T, SMG_DOM_SQUARE>,
+  const void* fns[5] = {(const void*)k_coarse_cycle<T, SMG_DOM_SQUARE>,
                         (const void*)k_coarse_cycle_b<T, SMG_DOM_SQUARE>,
                         (const void*)k_coarse_cycle<T, SMG_DOM_LSHAPE>,
-                        (const void*)k_coarse_cycle_b<T, SMG_DOM_LSHAPE>};
+                        (const void*)k_coarse_cycle_b<T, SMG_DOM_LSHAPE>,
+                        (const void*)k_coarse_cycle<T, SMG_DOM_UNIONJACK>};
   for (const void* f : fns) {
     const int e = (int)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != 0) return e;

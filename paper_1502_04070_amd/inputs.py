@@ -75,3 +75,16 @@ def adjoint_instances(n_inst: int = 16, N: int = 256, seed: int = 0):
         ut, _ = random_state(N, 10000 + i)
         out.append((float(betas[i]), f, ut))
     return out
+
+
+def section6_fields(N: int):
+    """The fields of the experiment of Section 6 at the lattice points:
+    u = phi (y - 1/2, 1/2 - x), p = phi, phi = max(0, min(1, 2 - 4 |x - (1/2, 1/2)|))
+    (nodal values; the paper projects them in L2, which needs quadrature)."""
+    su, sp = lattice_shapes(N)
+    a = np.arange(2 * N + 1) / (2 * N)
+    X, Y = np.meshgrid(a, a)                       # [b, a]
+    phi = np.clip(2.0 - 4.0 * np.hypot(X - 0.5, Y - 0.5), 0.0, 1.0)
+    u = np.stack([phi * (Y - 0.5), phi * (0.5 - X)])
+    u[:, 0, :] = u[:, -1, :] = u[:, :, 0] = u[:, :, -1] = 0.0
+    return u, np.ascontiguousarray(phi[::2, ::2])
