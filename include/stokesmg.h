@@ -87,7 +87,8 @@ typedef struct {
   int fuse_depth;   /* normal-equation steps per launch on levels with 8 x 8
                        tiles: 1 or 2 (default 2)                               */
   int coarse_max_n; /* largest grid (squares per side) of the single-workgroup
-                       coarse kernel (default 8; the coarsest level always)    */
+                       coarse kernel (default 8, 16 on the union-jack grid;
+                       the coarsest level always)                              */
   int tile_x;       /* squares per tile row of the normal-equation kernels: 8
                        or 16 (default: 16 for N >= 128, else 8)                */
   int domain;       /* SMG_DOMAIN_SQUARE (default): the unit square;

@@ -894,8 +894,9 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     H->Lc = -1;
     // largest grid done by the single-workgroup kernel (default 8 squares per
     // side: from N = 16 on, the grid kernels with two smoothing steps per
-    // launch finish a level sooner than one workgroup does)
-    const int cmax = prm.coarse_max_n > 0 ? prm.coarse_max_n : 8;
+    // launch finish a level sooner than one workgroup does; 16 on the
+    // union-jack grid, whose unfused W-cycles visit the coarse levels often)
+    const int cmax = prm.coarse_max_n > 0 ? prm.coarse_max_n : (prm.domain == SMG_DOM_UNIONJACK ? 16 : 8);
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
       if ((prm.n0 << l) > cmax) break;
       const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));
