@@ -113,6 +113,101 @@ def cpu_baseline(n_cycles=30):
                       f"({len(BETAS) * n_cycles} cycles, {t_total:.1f} s, 1 thread, setup excluded)"}
 
 
+def _oracle_rhs(h, F, G):
+    import numpy as np
+    from tests import lattice as lat
+    d = h.discs[-1]
+    fn, gn = lat.lattice_to_nodal(d, F, G)
+    gn = gn - (h.top.m @ gn) / h.top.m.sum()
+    return np.concatenate(d.load(fn, gn))
+
+
+def _pool_worker(spec, barrier, queue):
+    """One instance of a pooled oracle sample: setup, wait for every worker,
+    then `cycles` V(2,2) iterates with residual norms, timed (wall clock)."""
+    import numpy as np
+    from oracle import multigrid as mg
+    from paper_1502_04070_amd import inputs
+    os.environ["OMP_NUM_THREADS"] = "1"
+    kind, N, beta, seed, cycles = spec
+    h = mg.Hierarchy("same_diag", int(round(np.log2(N // 2))), beta, n0=2)
+    if kind == "normal_fg":
+        F, G = inputs.normal_fg(N, seed)
+    else:
+        F, G = inputs.normal_fg(N, seed, with_g=False)
+    f = _oracle_rhs(h, F, G)
+    x = np.zeros(h.top.n)
+    barrier.wait()
+    t0 = time.time()
+    for _ in range(cycles):
+        x = mg.top_cycle(h, x, f, mg.Params())
+        np.linalg.norm(mg.residual(h.top, x, f))
+    queue.put((dofs(N) * cycles, t0, time.time()))
+
+
+def _pooled(specs):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(len(specs))
+    queue = ctx.Queue()
+    procs = [ctx.Process(target=_pool_worker, args=(sp, barrier, queue)) for sp in specs]
+    for pr in procs:
+        pr.start()
+    res = [queue.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+    work = sum(r[0] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    return {"dof_cycles_per_s": work / wall, "processes": len(specs), "wall_s": wall}
+
+
+def cpu_extras():
+    """The oracle (SciPy CSR, FP64) timed on the host for the other workloads:
+    one thread for the two-grid case, the h = 1/128 betas and h = 1/512 (to
+    tolerance), and a process pool (one process per sampled instance, at most
+    16) for the uneven batch and the adjoint instances (10 iterates each)."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle import multigrid as mg
+    from paper_1502_04070_amd import inputs
+
+    out = {"host_cores": os.cpu_count()}
+    try:
+        out["host_cpu"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        out["host_cpu"] = None
+
+    def solve_timed(h, f, tol):
+        t0 = time.perf_counter()
+        res = mg.solve(h, f, mg.Params(), tol=tol, maxit=500)
+        dt = time.perf_counter() - t0
+        return {"iterations": res.iters, "time_to_tol_s": dt, "s_per_cycle": dt / max(res.iters, 1),
+                "status": res.status}
+
+    with threadpool_limits(1):
+        h = mg.Hierarchy("same_diag", 1, 1.0, n0=4)
+        out["two_grid_h8"] = solve_timed(h, _oracle_rhs(h, *inputs.uniform_f(8, seed=0)), 1e-8)
+        rec = {}
+        for beta in BETAS:
+            h = mg.Hierarchy("same_diag", 6, beta, n0=2)
+            rec[str(beta)] = solve_timed(h, _oracle_rhs(h, *inputs.uniform_f(N_GRID, seed=0)), TOL)
+        out["h128_betas"] = rec
+        rec = {}
+        for beta in (1.0, 1e4):
+            h = mg.Hierarchy("same_diag", 8, beta, n0=2)
+            rec[str(beta)] = solve_timed(h, _oracle_rhs(h, *inputs.smooth_plus_noise(512, seed=0)), 1e-10)
+        out["h512_fp64_to_1e-10"] = rec
+    nproc = max(1, min(16, os.cpu_count() or 1))
+    insts = inputs.batched_instances()
+    specs = [("normal_fg", N, beta, [i, 0], 10) for i, (N, beta, _) in enumerate(insts[:nproc])]
+    out["batch_64x4_sample"] = dict(_pooled(specs), sample=f"instances 0..{nproc - 1} (rhs 0), 10 iterates each")
+    ad = inputs.adjoint_instances()
+    specs = [("forward", 256, beta, i, 10) for i, (beta, _, _) in enumerate(ad[:nproc])]
+    out["adjoint_16x_h256_forward_sample"] = dict(_pooled(specs),
+                                                  sample=f"instances 0..{nproc - 1}, forward iterates, 10 each")
+    return out
+
+
 def copy_calibration(mib=512, reps=5):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the reference
     kernel against which the HBM byte counters are scaled (it reads and writes
@@ -305,6 +400,25 @@ def extras():
             del hh
         rec[f"beta={beta:g}"] = r
     out["l_shape_h256"] = rec
+
+    # h = 1/128, the five betas: iterates to 1e-8 of NE and Uzawa V(3,3) and W(3,3)
+    F128, G128 = inputs.uniform_f(N_GRID, seed=0)
+    rec = {"tol": TOL}
+    for name, kw in (("ne_V33", dict(smoother="ne", nu_pre=3, nu_post=3)),
+                     ("uzawa_V33", dict(smoother="uzawa", nu_pre=3, nu_post=3)),
+                     ("ne_W33", dict(smoother="ne", nu_pre=3, nu_post=3, gamma=2)),
+                     ("uzawa_W33", dict(smoother="uzawa", nu_pre=3, nu_post=3, gamma=2))):
+        r = {}
+        for beta in BETAS:
+            hh = Hierarchy(N_GRID, beta, **kw)
+            fu, gp = hh.load(torch.from_numpy(F128).cuda(), torch.from_numpy(G128).cuda())
+            hh.solve(fu, gp, rtol=TOL, maxit=500)
+            (_, _, inf), t_s = _timed(lambda: hh.solve(fu, gp, rtol=TOL, maxit=500))
+            r[str(beta)] = {"iterations": inf.iters if inf.status == "ok" else None,
+                            "status": inf.status, "time_to_tol_ms": 1e3 * t_s}
+            del hh
+        rec[name] = r
+    out["h128_smoothers_cycles"] = rec
     torch.cuda.empty_cache()
 
     # the measurement protocol of Section 6 on the union-jack grid (Tables 2
@@ -349,7 +463,12 @@ def main():
                     help="instances of the probe batch (5: the betas of the main workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
+    ap.add_argument("--cpu-extras", action="store_true",
+                    help="only time the oracle on the host for the other workloads (no GPU)")
     args = ap.parse_args()
+    if args.cpu_extras:
+        print(json.dumps({"cpu_extras": cpu_extras()}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
               "(independent instances would be spread over GPUs, a single large one split into strips "
@@ -387,7 +506,11 @@ def main():
     sched_batch, rec_batch = tune.schedule_for([N_GRID] * len(BETAS), BETAS, iters=10)
     sched_single, rec_single = tune.schedule_for([N_GRID], [1.0], iters=10)
     t_tune = time.perf_counter() - t_tune
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     batch = Batch([N_GRID] * len(BETAS), BETAS, schedule=sched_batch)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
     loads = [h.load(Fd, Gd) for h in batch.instances]       # resident load vectors
     fus = [a for a, _ in loads]
     gps = [b for _, b in loads]
@@ -468,6 +591,7 @@ def main():
                      "single": sched_single, "single_ms_per_iterate": rec_single["ms_per_iterate"],
                      "tuning_s": t_tune},
         "time_to_tol_ms_batch": 1e3 * elapsed / args.steps,
+        "setup_ms_batch": 1e3 * t_setup,
         "time_to_tol_ms_single": tt64,
         "fp32_refine": {
             "value": dofs(N_GRID) * sum(mixed_its) / mixed_elapsed,

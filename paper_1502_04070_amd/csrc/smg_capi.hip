@@ -482,6 +482,20 @@ void copy_vec(Level& L, Vec<T> dst, Vec<T> src, const int* done, hipStream_t s) 
 
 // Fused iterate on level l for (x, f).  Returns the buffer holding the
 // result: x itself, or the level's t buffer (its ping-pong partner).
+// one fused Uzawa step from cur into its ping-pong partner alt
+template <class T>
+void uzawa_fused(Level& L, Vec<T> cur, Vec<T> f, Vec<T> alt, bool zg, const int* done, hipStream_t s) {
+  UZJob<T> J{};
+  J.L = Sel<T>::c(L);
+  J.xu = cur.u; J.xp = cur.p;
+  J.fu = f.u; J.fp = f.p;
+  J.ou = alt.u; J.op = alt.p;
+  J.tau = T(L.tau);
+  J.sigma = T(L.sigma);
+  J.done = done;
+  launch_uz<T>(J, zg, s);
+}
+
 template <class T>
 Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
   if (l <= H->Lc) {
@@ -516,9 +530,8 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       std::swap(cur, alt);
       k += two ? 2 : 1;
     } else {
-      // Uzawa: three passes through the level's t buffer, result in place
-      // (t is free here: the iterate stays in cur)
-      smooth_step<T>(prm, L, cur, f, alt, z, done, s);
+      uzawa_fused<T>(L, cur, f, alt, z, done, s);
+      std::swap(cur, alt);
       ++k;
     }
     z = false;
@@ -571,7 +584,8 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       std::swap(cur, alt);
       k += two ? 2 : 1;
     } else {
-      smooth_step<T>(prm, L, cur, f, alt, false, done, s);
+      uzawa_fused<T>(L, cur, f, alt, false, done, s);
+      std::swap(cur, alt);
       ++k;
     }
   }

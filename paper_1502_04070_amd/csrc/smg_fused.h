@@ -21,6 +21,26 @@ struct NEJob {
   const int* done;
 };
 TileShape ne_tile_shape(int N);
+
+// One Uzawa-type smoothing step (Section 4), all three half-steps in one
+// launch on 16 x 8 tiles (square and L-shaped domains)
+template <class T>
+struct UZJob {
+  LevelCoef<T> L;
+  const T* xu;
+  const T* xp;        // input iterate (not read when it is known to be zero)
+  const T* fu;
+  const T* fp;        // right-hand side
+  T* ou;
+  T* op;              // output iterate; must not alias the input
+  T tau, sigma;
+  const int* done;
+};
+int uz_tiles(int N);
+template <class T>
+void launch_uz(const UZJob<T>& J, bool zero_guess, hipStream_t s);
+template <class T>
+void launch_uz_b(const JobArg<UZJob<T>>& A, int nb, bool zero_guess, int dom, hipStream_t s);
 // two normal-equation steps in one launch (8 x 8 tiles; levels with N < 128):
 // the output is the iterate after both steps; the partial field is not used
 template <class T>

@@ -655,6 +655,194 @@ template void launch_ne2_b<double>(const JobArg<NEJob<double>>&, int, bool, bool
 template void launch_ne2_b<float>(const JobArg<NEJob<float>>&, int, bool, bool, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// k_uz: one Uzawa-type smoothing step (Section 4) on a TX x TY tile of squares
+// ---------------------------------------------------------------------------
+// The three half-steps in one launch:
+//   1. u' = u + tau Ahat^-1 (f - A u - B^T p)   on the tile plus two squares
+//   2. dp = -sigma Shat^-1 (g - B u')            on the tile's vertices plus one
+//   3. u_new = u' - tau Ahat^-1 B^T dp, p_new = p + dp   on the tile
+// The velocity row of a node reads u within one square and p at the
+// vertices of the squares around it, so step 1 on the tile plus two needs u
+// and p on the tile plus three squares; the pressure row of a vertex reads u'
+// within one square.  Windows (lattice of the points owned by their squares,
+// zero outside the interior of the velocity space and the grid):
+//   X  u, squares [i0 - 3, i0 + TX + 2]      XP p, vertices [i0 - 3, i0 + TX + 2]
+//   H  u', squares [i0 - 2, i0 + TX + 1]     D  dp, vertices [i0 - 1, i0 + TX]
+
+template <class T, int TX, int TY, bool ZG, int DOM>
+__device__ __forceinline__ void uz_tile(const UZJob<T>& J, int tile) {
+  constexpr int NT = 2 * TX * TY;
+  constexpr int XW = 2 * TX + 12, XH = 2 * TY + 12;     // u: origin (2 i0 - 6, 2 j0 - 6)
+  constexpr int PW = TX + 6, PH = TY + 6;               // p: origin (i0 - 3, j0 - 3)
+  constexpr int HW = 2 * TX + 8, HH = 2 * TY + 8;       // u': origin (2 i0 - 4, 2 j0 - 4)
+  constexpr int DW = TX + 2, DH = TY + 2;               // dp: origin (i0 - 1, j0 - 1)
+  constexpr int S1W = TX + 4, S1 = (TX + 4) * (TY + 4); // squares of step 1
+  static_assert(S1 <= NT, "one step-1 square per thread");
+  __shared__ T sx[2][XH][XW];
+  __shared__ T sxp[PH * PW];
+  __shared__ T sh[2][HH][HW];
+  __shared__ T sd[DH * DW];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int ntx = (N + TX) / TX;
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
+  // requested before the first wait: the done flag, this thread's step-1
+  // right-hand side and its step-2 g and Shat^-1
+  const int dn = J.done ? *J.done : 0;
+  const int c1i = tid % S1W, c1j = tid / S1W;
+  const int s1i = i0 - 2 + c1i, s1j = j0 - 2 + c1j;
+  const bool act1 = tid < S1;
+  T f1[8];
+#pragma unroll
+  for (int cls = 0; cls < 4; ++cls) {
+    const int a = 2 * s1i + (cls & 1), b = 2 * s1j + (cls >> 1);
+    const bool in = act1 && interior(a, b);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f1[2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+  }
+  const int v2i = tid % DW, v2j = tid / DW;
+  const int vi = i0 - 1 + v2i, vj = j0 - 1 + v2j;
+  const bool act2 = tid < DW * DH && dom_p(N, DOM, vi, vj);
+  const T g2 = act2 ? J.fp[(size_t)vj * NP + vi] : T(0);
+  const T s2 = act2 ? J.L.sinv[(size_t)vj * NP + vi] : T(0);
+
+  if constexpr (!ZG) {
+    for (int e = tid; e < XW * XH; e += NT) {
+      const int la = e % XW, lb = e / XW;
+      const int a = 2 * i0 - 6 + la, b = 2 * j0 - 6 + lb;
+      const bool in = interior(a, b);
+      const size_t g = (size_t)b * M + a;
+      sx[0][lb][la] = in ? J.xu[g] : T(0);
+      sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
+    }
+    for (int e = tid; e < PW * PH; e += NT) {
+      const int i = i0 - 3 + e % PW, j = j0 - 3 + e / PW;
+      sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+    }
+    __syncthreads();
+  }
+  if (dn) return;   // uniform across the workgroup
+
+  // ---- step 1: u' on the tile plus two squares
+  if (act1) {
+    T y[9];
+    if constexpr (ZG) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) y[k] = T(0);
+    } else {
+      cell_apply<T, true, true, XH, XW, PW>(J.L, sx, 2 * c1i + 2, 2 * c1j + 2, sxp, c1i + 1, c1j + 1, y);
+    }
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * s1i + DA, 2 * s1j + DB);
+      const T d = J.tau * J.L.adinv[cls];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T x0 = T(0);
+        if constexpr (!ZG) x0 = sx[c][2 * c1j + 2 + DB][2 * c1i + 2 + DA];
+        sh[c][2 * c1j + DB][2 * c1i + DA] = in ? x0 + d * (f1[2 * cls + c] - y[2 * cls + c]) : T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- step 2: dp on the tile's vertices plus one
+  if (tid < DW * DH) {
+    auto U0 = [&](int da, int db) -> T { return sh[0][2 * v2j + 2 + db][2 * v2i + 2 + da]; };
+    auto U1 = [&](int da, int db) -> T { return sh[1][2 * v2j + 2 + db][2 * v2i + 2 + da]; };
+    const T bu = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+    sd[tid] = act2 ? -J.sigma * s2 * (g2 - bu) : T(0);
+  }
+  __syncthreads();
+
+  // ---- step 3: u_new and p_new on the tile; two threads per square
+  {
+    const int part = tid / (TX * TY), q = tid % (TX * TY);
+    const int tx = q % TX, ty = q / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i <= N && j <= N) {
+      auto PA = [&](int di, int dj) -> T { return sd[(ty + 1 + dj) * DW + (tx + 1 + di)]; };
+      auto Un = [&](int c, int da, int db) -> T { return T(0); };
+      auto emit = [&](int cls, T z0, T z1) {
+        const int DA = cls & 1, DB = cls >> 1;
+        const int a = 2 * i + DA, b = 2 * j + DB;
+        if (a > 2 * N || b > 2 * N) return;
+        const bool in = interior(a, b);
+        const size_t g = (size_t)b * M + a;
+        const T d = J.tau * J.L.adinv[cls];
+        J.ou[g] = in ? sh[0][2 * ty + 4 + DB][2 * tx + 4 + DA] - d * z0 : T(0);
+        J.ou[(size_t)M * M + g] = in ? sh[1][2 * ty + 4 + DB][2 * tx + 4 + DA] - d * z1 : T(0);
+      };
+      T z0, z1;
+      if (part == 0) {
+        cell_vel<0, T, false, true>(J.L, Un, PA, z0, z1);
+        emit(0, z0, z1);
+        cell_vel<1, T, false, true>(J.L, Un, PA, z0, z1);
+        emit(1, z0, z1);
+      } else {
+        cell_vel<2, T, false, true>(J.L, Un, PA, z0, z1);
+        emit(2, z0, z1);
+        cell_vel<3, T, false, true>(J.L, Un, PA, z0, z1);
+        emit(3, z0, z1);
+        T p0 = T(0);
+        if constexpr (!ZG) p0 = sxp[(ty + 3) * PW + tx + 3];
+        J.op[(size_t)j * NP + i] = dom_p(N, DOM, i, j) ? p0 + PA(0, 0) : T(0);
+      }
+    }
+  }
+}
+
+template <class T, int TX, int TY, bool ZG, int DOM>
+__global__ __launch_bounds__(2 * TX* TY) void k_uz(UZJob<T> J) {
+  uz_tile<T, TX, TY, ZG, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class T, int TX, int TY, bool ZG, bool PACK, int DOM>
+__global__ __launch_bounds__(2 * TX* TY) void k_uz_b(const JobArg<UZJob<T>> A) {
+  int tile;
+  const UZJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  uz_tile<T, TX, TY, ZG, DOM>(J, tile);
+}
+
+int uz_tiles(int N) { return ((N + 16) / 16) * ((N + 8) / 8); }
+
+template <class T, int DOM>
+static void launch_uz_dom(const UZJob<T>& J, bool zg, hipStream_t s) {
+  const int nb = uz_tiles(J.L.N);
+  if (zg) k_uz<T, 16, 8, true, DOM><<<nb, 256, 0, s>>>(J);
+  else k_uz<T, 16, 8, false, DOM><<<nb, 256, 0, s>>>(J);
+}
+
+template <class T>
+void launch_uz(const UZJob<T>& J, bool zg, hipStream_t s) {
+  if (J.L.dom == SMG_DOM_LSHAPE) launch_uz_dom<T, SMG_DOM_LSHAPE>(J, zg, s);
+  else launch_uz_dom<T, SMG_DOM_SQUARE>(J, zg, s);
+}
+template void launch_uz<double>(const UZJob<double>&, bool, hipStream_t);
+template void launch_uz<float>(const UZJob<float>&, bool, hipStream_t);
+
+template <class T, int DOM>
+static void launch_uz_b_dom(const JobArg<UZJob<T>>& A, int nb, bool zg, hipStream_t s) {
+  if (A.n > 0) {
+    if (zg) k_uz_b<T, 16, 8, true, true, DOM><<<nb, 256, 0, s>>>(A);
+    else k_uz_b<T, 16, 8, false, true, DOM><<<nb, 256, 0, s>>>(A);
+  } else {
+    if (zg) k_uz_b<T, 16, 8, true, false, DOM><<<nb, 256, 0, s>>>(A);
+    else k_uz_b<T, 16, 8, false, false, DOM><<<nb, 256, 0, s>>>(A);
+  }
+}
+
+template <class T>
+void launch_uz_b(const JobArg<UZJob<T>>& A, int nb, bool zg, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_uz_b_dom<T, SMG_DOM_LSHAPE>(A, nb, zg, s);
+  else launch_uz_b_dom<T, SMG_DOM_SQUARE>(A, nb, zg, s);
+}
+template void launch_uz_b<double>(const JobArg<UZJob<double>>&, int, bool, int, hipStream_t);
+template void launch_uz_b<float>(const JobArg<UZJob<float>>&, int, bool, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // k_resid_restrict: F_c = P^T (F - A x) on an 8 x 8 tile of coarse squares
 // ---------------------------------------------------------------------------
 
