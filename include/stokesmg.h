@@ -64,7 +64,11 @@ enum {
   SMG_ESINGULAR = -4,   /* coarsest-grid matrix numerically singular */
   SMG_NOCONV = 1,       /* maxit reached; outputs hold the last iterate */
   SMG_DIVERGED = 2,     /* relative residual above 1e6; last iterate returned */
-  SMG_ENONFINITE = 3    /* NaN or Inf in the residual; last iterate returned */
+  SMG_ENONFINITE = 3,   /* NaN or Inf in the residual; last iterate returned */
+  SMG_EINCOMPAT = 4     /* no convergence and the pressure data are not
+                           compatible: |1^T g_p| > 1e-9 sum |g_p| (the system
+                           needs int g = 0, see smg_project_mean); last
+                           iterate returned                                   */
 };
 
 enum { SMG_SMOOTHER_NE = 0, SMG_SMOOTHER_UZAWA = 1 };
@@ -226,7 +230,7 @@ int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* u
  * (u, p) are the initial guess on entry and the solution on return (mean-free
  * pressure).  iters, relres and history (maxit doubles, relative residual
  * after each iterate) may be NULL; they are HOST pointers.  Synchronous.
- * Returns SMG_OK, SMG_NOCONV, SMG_DIVERGED or SMG_ENONFINITE (soft) or a
+ * Returns SMG_OK, SMG_NOCONV, SMG_DIVERGED, SMG_ENONFINITE or SMG_EINCOMPAT (soft) or a
  * hard error.
  */
 int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxit,

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstokesmg
 
 SMG_OK = 0
 STATUS = {0: "ok", -1: "einval", -2: "ehip", -3: "enomem", -4: "esingular",
-          1: "noconv", 2: "diverged", 3: "nonfinite"}
+          1: "noconv", 2: "diverged", 3: "nonfinite", 4: "incompatible"}
 SMOOTHERS = {"ne": 0, "uzawa": 1}
 DOMAINS = {"square": 0, "l_shape": 1, "union_jack": 2}
 

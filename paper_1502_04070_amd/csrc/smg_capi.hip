@@ -719,10 +719,14 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
   top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, mixed ? T.t.u : nullptr, mixed ? T.t.p : nullptr,
                nullptr, s);
   launch_init_state(T.partial, T.ntiles, H->fdots, H->st, s);
+  launch_psum(T.N, H->dom, T.f.p, H->red, H->enorm, s);
   int rc = launch_status("solve init");
   if (rc) return rc;
+  double psum[2];
   HIPCHK(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(psum, H->enorm, sizeof(psum), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const bool incompatible = std::fabs(psum[0]) > SMG_COMPAT_TOL * psum[1];
   double rel_prev = H->st_host->relres;
   int launched = 0, chunk = 2;
   while (!H->st_host->done && launched < maxit) {
@@ -749,6 +753,9 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = it;
   if (relres) *relres = H->st_host->relres;
+  if (H->st_host->done != 1 && incompatible)
+    return fail(SMG_EINCOMPAT, "no convergence: the pressure data are not compatible (1^T g_p = %g, sum |g_p| = %g)",
+                psum[0], psum[1]);
   switch (H->st_host->done) {
     case 1: return SMG_OK;
     case 2: return fail(SMG_DIVERGED, "diverged after %d iterates (relres %g)", it, H->st_host->relres);

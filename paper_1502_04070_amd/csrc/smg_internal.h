@@ -210,6 +210,10 @@ void launch_reduce(const double* partials, int np, double* out, hipStream_t s);
 // Section 6 error measure pieces of (u, p) - (us, ps); scratch of
 // enorm_scratch(N) doubles, out: 4 doubles (see the kernels)
 int enorm_scratch(int N);
+// out2 = (1^T gp, sum |gp|) over the domain's vertices (scratch as enorm_scratch)
+void launch_psum(int N, int dom, const double* gp, double* red, double* out2, hipStream_t s);
+// relative size of 1^T gp above which the pressure data count as incompatible
+constexpr double SMG_COMPAT_TOL = 1e-9;
 void launch_error_norm(int N, int dom, double bh2, const double* ahat4, const double* sinv, const double* u,
                        const double* p, const double* us, const double* ps, double* red, double* out,
                        hipStream_t s);

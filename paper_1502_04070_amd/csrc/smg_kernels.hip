@@ -1094,6 +1094,36 @@ __global__ __launch_bounds__(256) void k_enorm_u(int N, int dom, double bh2, dou
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// 1^T gp and sum |gp| over the domain's vertices (two partial arrays of nb
+// entries): the data are compatible (int g = 0) when the first vanishes
+__global__ __launch_bounds__(256) void k_psum_partial(int N, int dom, const double* __restrict__ gp,
+                                                      double* partials, int nb) {
+  __shared__ double red[4];
+  const int n = (N + 1) * (N + 1);
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int e = blockIdx.x * 1024 + k * 256 + threadIdx.x;
+    if (e < n && dom_p(N, dom, e % (N + 1), e / (N + 1))) {
+      s1 += gp[e];
+      s2 += fabs(gp[e]);
+    }
+  }
+  const double t1 = block_sum<256>(s1, red);
+  __syncthreads();
+  const double t2 = block_sum<256>(s2, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = t1;
+    partials[nb + blockIdx.x] = t2;
+  }
+}
+
+void launch_psum(int N, int dom, const double* gp, double* red, double* out2, hipStream_t s) {
+  const int nb = ((N + 1) * (N + 1) + 1023) / 1024;
+  k_psum_partial<<<nb, 256, 0, s>>>(N, dom, gp, red, nb);
+  k_reduce_final<<<1, 256, 0, s>>>(red, nb, out2);
+  k_reduce_final<<<1, 256, 0, s>>>(red + nb, nb, out2 + 1);
+}
+
 int enorm_scratch(int N) { return std::max(dot_blocks(N, 0), 2 * ((N + 1) * (N + 1) + 1023) / 1024 + 2); }
 
 // out[0..1]: mean pieces, out[2]: pressure part, out[3]: velocity part

@@ -188,3 +188,24 @@ def test_mixed_precision_solve_reaches_fp64_accuracy(beta):
     # the FP64 solve takes about as many cycles (a linear iterate is the same in both forms)
     _, _, i64 = gh.solve(FU, GP, rtol=1e-10, maxit=400)
     assert abs(i64.iters - info.iters) <= max(3, 0.1 * i64.iters)
+
+
+def test_incompatible_pressure_data_reported():
+    """int g != 0 makes the saddle system unsolvable (B^T 1 = 0): the solve
+    cannot converge and says why; the same data made mean-free converge.
+    Batched: the incompatible instance alone is flagged."""
+    from paper_1502_04070_amd import Batch
+    N = 16
+    gh = gpu_hier(N, 1.0)
+    F, G = inputs.normal_fg(N, seed=70)
+    fu, gp = gh.load(dev(F), dev(G))
+    _, _, info = gh.solve(fu, gp, rtol=1e-8, maxit=40)
+    assert info.status == "incompatible", info
+    Gd = dev(G)
+    gh.project_mean(Gd)
+    fu2, gp2 = gh.load(dev(F), Gd)
+    _, _, info = gh.solve(fu2, gp2, rtol=1e-8, maxit=300)
+    assert info.status == "ok", info
+    B = Batch([N, N], [1.0, 1.0])
+    _, _, infos = B.solve([fu, fu2], [gp, gp2], rtol=1e-8, maxit=300)
+    assert [i.status for i in infos] == ["incompatible", "ok"], infos
