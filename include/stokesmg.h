@@ -91,8 +91,7 @@ typedef struct {
   int fuse_depth;   /* normal-equation steps per launch on levels with 8 x 8
                        tiles: 1 or 2 (default 2)                               */
   int coarse_max_n; /* largest grid (squares per side) of the single-workgroup
-                       coarse kernel (default 8, 16 on the union-jack grid;
-                       the coarsest level always)                              */
+                       coarse kernel (default 8; the coarsest level always)    */
   int tile_x;       /* squares per tile row of the normal-equation kernels: 8
                        or 16 (default: 16 for N >= 128, else 8)                */
   int domain;       /* SMG_DOMAIN_SQUARE (default): the unit square;
@@ -105,9 +104,8 @@ typedef struct {
                        SMG_DOMAIN_UNIONJACK: the unit square on the grid of the
                        experiments of Section 6 (the coarsest 2 x 2 grid with
                        the diagonals meeting at the centre, refined
-                       uniformly); needs an even n0.  Runs the unfused
-                       kernels (unfused is set to 1) and single hierarchies
-                       only (no batches).                                      */
+                       uniformly); needs an even n0; single hierarchies only
+                       (no batches).                                           */
 } smg_params;
 
 enum { SMG_DOMAIN_SQUARE = 0, SMG_DOMAIN_LSHAPE = 1, SMG_DOMAIN_UNIONJACK = 2 };

@@ -810,9 +810,6 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     return fail(SMG_EINVAL, "unknown domain %d", prm.domain);
   if (prm.domain == SMG_DOM_LSHAPE && prm.n0 % 2) return fail(SMG_EINVAL, "the L-shaped domain needs an even n0");
   if (prm.domain == SMG_DOM_UNIONJACK && prm.n0 % 2) return fail(SMG_EINVAL, "the union-jack grid needs an even n0");
-  // the fused kernels assume one diagonal direction: the union-jack grid
-  // runs the unfused iterate
-  if (prm.domain == SMG_DOM_UNIONJACK) prm.unfused = 1;
   if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
   int L = 0;
   {
@@ -915,9 +912,8 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     H->Lc = -1;
     // largest grid done by the single-workgroup kernel (default 8 squares per
     // side: from N = 16 on, the grid kernels with two smoothing steps per
-    // launch finish a level sooner than one workgroup does; 16 on the
-    // union-jack grid, whose unfused W-cycles visit the coarse levels often)
-    const int cmax = prm.coarse_max_n > 0 ? prm.coarse_max_n : (prm.domain == SMG_DOM_UNIONJACK ? 16 : 8);
+    // launch finish a level sooner than one workgroup does)
+    const int cmax = prm.coarse_max_n > 0 ? prm.coarse_max_n : 8;
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
       if ((prm.n0 << l) > cmax) break;
       const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));

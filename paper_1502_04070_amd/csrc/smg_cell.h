@@ -109,6 +109,116 @@ __device__ __forceinline__ void cell_apply(const LevelCoef<T>& L, const T (*U)[U
   cell_apply_acc<T, HU, HP>(L, UA, PA, y);
 }
 
+// ---- rows on either grid: DOM = SMG_DOM_UNIONJACK sums them square by
+// square (smg_uj.h), every other domain uses the lattice stencils.  (i, j) is
+// the square in global indices (the diagonal direction depends on it), U
+// reads component c at an offset from the square's V point and P the
+// pressure at an offset from its vertex.
+
+// all nine rows of square (i, j) and 1 / Ahat at its four nodes
+template <class T, bool HU, bool HP, int DOM, class UA, class PA>
+__device__ __forceinline__ void sq_rows(const LevelCoef<T>& L, int i, int j, UA U, PA P, T y[9], T ad[4]) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int N = L.N;
+    auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+    T d;
+    uj_vel_rows<0, T>(L.bh2, L.h, HU, HP, U, P, OR, y[0], y[1], d);
+    ad[0] = T(1) / d;
+    uj_vel_rows<1, T>(L.bh2, L.h, HU, HP, U, P, OR, y[2], y[3], d);
+    ad[1] = T(1) / d;
+    uj_vel_rows<2, T>(L.bh2, L.h, HU, HP, U, P, OR, y[4], y[5], d);
+    ad[2] = T(1) / d;
+    uj_vel_rows<3, T>(L.bh2, L.h, HU, HP, U, P, OR, y[6], y[7], d);
+    ad[3] = T(1) / d;
+    y[8] = HU ? uj_p_row<T>(L.h, U, OR) : T(0);
+  } else {
+    cell_apply_acc<T, HU, HP>(L, U, P, y);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ad[k] = L.adinv[k];
+  }
+}
+
+// the two velocity rows of class CLS of square (i, j) and 1 / Ahat there
+template <int CLS, class T, bool HU, bool HP, int DOM, class UA, class PA>
+__device__ __forceinline__ void sq_vel(const LevelCoef<T>& L, int i, int j, UA U, PA P, T& y0, T& y1, T& ad) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int N = L.N;
+    auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+    T d;
+    uj_vel_rows<CLS, T>(L.bh2, L.h, HU, HP, U, P, OR, y0, y1, d);
+    ad = T(1) / d;
+  } else {
+    constexpr int DA = CLS & 1, DB = CLS >> 1;
+    auto Uc = [&](int c, int da, int db) -> T { return U(c, DA + da, DB + db); };
+    cell_vel<CLS, T, HU, HP>(L, Uc, P, y0, y1);
+    ad = L.adinv[CLS];
+  }
+}
+
+// the pressure row (B u) at the vertex of square (i, j)
+template <class T, int DOM, class UA>
+__device__ __forceinline__ T sq_prow(const LevelCoef<T>& L, int i, int j, UA U) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int N = L.N;
+    auto OR = [&](int di, int dj) { return uj_orient(N, i + di, j + dj); };
+    return uj_p_row<T>(L.h, U, OR);
+  } else {
+    auto U0 = [&](int da, int db) -> T { return U(0, da, db); };
+    auto U1 = [&](int da, int db) -> T { return U(1, da, db); };
+    return L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+  }
+}
+
+// restriction (transposed prolongation) at the coarse node of class CLS owned
+// by coarse square (I, J) of a grid with Nc squares per side; R(fa, fb) reads
+// the fine defect at (2A + fa, 2B + fb), (A, B) the coarse node
+template <int CLS, class T, int DOM, class FR>
+__device__ __forceinline__ T sq_res(int Nc, int I, int J, FR R) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    constexpr int CA = CLS & 1, CB = CLS >> 1;
+    const int A = 2 * I + CA, B = 2 * J + CB;
+    T v = T(0);
+#pragma unroll
+    for (int dj = (CB ? 0 : -1); dj <= 0; ++dj)
+#pragma unroll
+      for (int di = (CA ? 0 : -1); di <= 0; ++di) {
+        const int SI = I + di, SJ = J + dj;
+        if (SI < 0 || SJ < 0) continue;
+        const int o = uj_orient_c(Nc, SI, SJ);
+        const int cl = 3 * (CB - 2 * dj) + (CA - 2 * di);
+        for (int f = 0; f < 16; ++f) {
+          const double w = smg_stencil::UJ_PRO[o][f][cl];
+          if (w != 0.0) v += T(w) * R(4 * SI + (f & 3) - 2 * A, 4 * SJ + (f >> 2) - 2 * B);
+        }
+      }
+    return v;
+  } else {
+    return cell_res<CLS, T>(R);
+  }
+}
+
+// pressure restriction at coarse vertex (I, J); Rp(di, dj) reads the fine
+// defect at (2I + di, 2J + dj)
+template <class T, int DOM, class FR>
+__device__ __forceinline__ T sq_resp(int Nc, int I, int J, FR Rp) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    T v = T(0);
+    for (int dj = -1; dj <= 0; ++dj)
+      for (int di = -1; di <= 0; ++di) {
+        const int SI = I + di, SJ = J + dj;
+        if (SI < 0 || SJ < 0) continue;
+        const int o = uj_orient_c(Nc, SI, SJ), q = 2 * (-dj) + (-di);
+        for (int vv = 0; vv < 4; ++vv) {
+          const double w = smg_stencil::UJ_PP[o][vv][q];
+          if (w != 0.0) v += T(w) * Rp(2 * di + (vv & 1), 2 * dj + (vv >> 1));
+        }
+      }
+    return v;
+  } else {
+    return Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1));
+  }
+}
+
 // Sum over the workgroup (NT a multiple of 64); result valid in thread 0.
 template <int NT>
 __device__ __forceinline__ double wg_sum(double v, double* red) {

@@ -50,21 +50,6 @@ __device__ __forceinline__ T pro_w(FZ Z) {
   else return SMG_PRO_33(Z);
 }
 
-// Adds P z to the 16 fine lattice points (4I + ra, 4J + rb) of coarse square
-// (I, J): X(ra, rb) is a reference to the destination, IN(ra, rb) tells
-// whether the fine point is an interior velocity node, Z(dA, dB) reads the
-// coarse value at (2I + dA, 2J + dB) (zero outside the coarse interior).
-template <class T, class FX, class FIN, class FZ>
-__device__ __forceinline__ void pro_block(FX X, FIN IN, FZ Z) {
-#define SMG_PB(RA, RB) \
-  if (IN(RA, RB)) X(RA, RB) += pro_w<RA, RB, T>(Z);
-  SMG_PB(0, 0) SMG_PB(1, 0) SMG_PB(2, 0) SMG_PB(3, 0)
-  SMG_PB(0, 1) SMG_PB(1, 1) SMG_PB(2, 1) SMG_PB(3, 1)
-  SMG_PB(0, 2) SMG_PB(1, 2) SMG_PB(2, 2) SMG_PB(3, 2)
-  SMG_PB(0, 3) SMG_PB(1, 3) SMG_PB(2, 3) SMG_PB(3, 3)
-#undef SMG_PB
-}
-
 // P1 interpolation of coarse pressure zp (Nc+1 per side) at fine vertex (i, j)
 template <class T>
 __device__ __forceinline__ T pro_p1(const T* zp, int Nc, int i, int j) {
@@ -75,6 +60,39 @@ __device__ __forceinline__ T pro_p1(const T* zp, int Nc, int i, int j) {
   if ((i & 1) && !(j & 1)) return T(0.5) * (Z(I, J) + Z(I + 1, J));
   if (!(i & 1) && (j & 1)) return T(0.5) * (Z(I, J) + Z(I, J + 1));
   return T(0.5) * (Z(I, J) + Z(I + 1, J + 1));
+}
+
+// the same on either grid (union jack: the table of the coarse square's
+// diagonal direction)
+template <int RA, int RB, class T, int DOM, class FZ>
+__device__ __forceinline__ T sq_pro(int Nc, int I, int J, FZ Z) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int o = uj_orient_c(Nc, I, J);
+    T v = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v += T(smg_stencil::UJ_PRO[o][4 * RB + RA][k]) * Z(k % 3, k / 3);
+    return v;
+  } else {
+    return pro_w<RA, RB, T>(Z);
+  }
+}
+
+template <class T, int DOM>
+__device__ __forceinline__ T sq_pro_p1(const T* zp, int Nc, int i, int j) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int NPc = Nc + 1, I = i >> 1, J = j >> 1;
+    const int o = uj_orient_c(Nc, I, J), v = 2 * (j & 1) + (i & 1);
+    T z = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ci = I + (q & 1), cj = J + (q >> 1);
+      const double w = smg_stencil::UJ_PP[o][v][q];
+      if (w != 0.0 && ci <= Nc && cj <= Nc) z += T(w) * zp[(size_t)cj * NPc + ci];
+    }
+    return z;
+  } else {
+    return pro_p1(zp, Nc, i, j);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -158,10 +176,10 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         switch (rb) {
 #define SMG_ROW(RB)                                                              \
   case RB:                                                                       \
-    if (interior(4 * I + 0, b)) v[0] += pro_w<0, RB, T>(Z);                      \
-    if (interior(4 * I + 1, b)) v[1] += pro_w<1, RB, T>(Z);                      \
-    if (interior(4 * I + 2, b)) v[2] += pro_w<2, RB, T>(Z);                      \
-    if (interior(4 * I + 3, b)) v[3] += pro_w<3, RB, T>(Z);                      \
+    if (interior(4 * I + 0, b)) v[0] += sq_pro<0, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 1, b)) v[1] += sq_pro<1, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 2, b)) v[2] += sq_pro<2, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 3, b)) v[3] += sq_pro<3, RB, T, DOM>(Nc, I, Jc, Z);    \
     break;
           SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
 #undef SMG_ROW
@@ -173,7 +191,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         const int li = e % XPW, lj = e / XPW;
         const int i = i0 - 2 + li, j = j0 - 2 + lj;
         T v = T(0);
-        if (dom_p(N, DOM, i, j)) v = J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j);
+        if (dom_p(N, DOM, i, j)) v = J.xp[(size_t)j * NP + i] + sq_pro_p1<T, DOM>(J.zp, N / 2, i, j);
         sxp[e] = v;
       }
     } else {
@@ -200,13 +218,11 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
   double nrm = 0.0;
   if (act1) {
     const int ci = c1i, cj = c1j, i = i1, j = j1;
-    T y[9];
-    if constexpr (ZG) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) y[k] = T(0);
-    } else {
-      cell_apply<T, true, true, XH, XW, XPW>(J.L, sx, 2 * ci + 2, 2 * cj + 2, sxp, ci + 1, cj + 1, y);
-    }
+    T y[9], ad[4];
+    auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+    auto PA = [&](int di, int dj) -> T { return sxp[(cj + 1 + dj) * XPW + (ci + 1 + di)]; };
+    if constexpr (ZG) sq_rows<T, false, false, DOM>(J.L, i, j, UA, PA, y, ad);
+    else sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
     const bool owned = ci >= 1 && ci <= TX && cj >= 1 && cj <= TY;
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
@@ -218,7 +234,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         T r = T(0);
         if (in) r = f1[2 * cls + c] - y[2 * cls + c];
         if (owned && in) nrm += (double)r * (double)r;
-        sy[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+        sy[c][2 * cj + DB][2 * ci + DA] = in ? ad[cls] * r : T(0);
       }
     }
     T rp = T(0);
@@ -238,7 +254,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
       auto UA = [&](int c, int da, int db) -> T { return sy[c][2 * ty + 2 + db][2 * tx + 2 + da]; };
       auto PA = [&](int di, int dj) -> T { return syp[(ty + 1 + dj) * YPW + (tx + 1 + di)]; };
       const T tau = J.tau;
-      auto emit = [&](int cls, T z0, T z1) {
+      auto emit = [&](int cls, T z0, T z1, T ad) {
         const int DA = cls & 1, DB = cls >> 1;
         const int a = 2 * i + DA, b = 2 * j + DB;
         if (a > 2 * N || b > 2 * N) return;
@@ -249,37 +265,22 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
           x0 = sx[0][2 * ty + 4 + DB][2 * tx + 4 + DA];
           x1 = sx[1][2 * ty + 4 + DB][2 * tx + 4 + DA];
         }
-        const T d = J.L.adinv[cls] * tau;
+        const T d = ad * tau;
         J.ou[g] = in ? x0 + d * z0 : T(0);
         J.ou[(size_t)M * M + g] = in ? x1 + d * z1 : T(0);
       };
+      T z0, z1, ad;
       if (part == 0) {
-        T z0, z1;
-        {
-          auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, db); };
-          cell_vel<0, T, true, true>(J.L, Uc, PA, z0, z1);
-          emit(0, z0, z1);
-        }
-        {
-          auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, db); };
-          cell_vel<1, T, true, true>(J.L, Uc, PA, z0, z1);
-          emit(1, z0, z1);
-        }
+        sq_vel<0, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(0, z0, z1, ad);
+        sq_vel<1, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(1, z0, z1, ad);
       } else {
-        T z0, z1;
-        {
-          auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, 1 + db); };
-          cell_vel<2, T, true, true>(J.L, Uc, PA, z0, z1);
-          emit(2, z0, z1);
-        }
-        {
-          auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, 1 + db); };
-          cell_vel<3, T, true, true>(J.L, Uc, PA, z0, z1);
-          emit(3, z0, z1);
-        }
-        auto U0 = [&](int da, int db) -> T { return UA(0, da, db); };
-        auto U1 = [&](int da, int db) -> T { return UA(1, da, db); };
-        const T zp = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+        sq_vel<2, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(2, z0, z1, ad);
+        sq_vel<3, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(3, z0, z1, ad);
+        const T zp = sq_prow<T, DOM>(J.L, i, j, UA);
         const size_t g = (size_t)j * NP + i;
         T xo = T(0);
         if constexpr (!ZG) xo = sxp[(ty + 2) * XPW + tx + 2];
@@ -296,7 +297,8 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 // The domain is a template parameter of every fused kernel (chosen by the
 // host launchers): a run-time test would cost the square's kernels a few
 // percent, and two instantiations inside one kernel would double its static
-// LDS.
+// LDS.  The single-instance launchers cover all three grids; the batched ones
+// the square and the L-shape (batches reject the union-jack grid).
 template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
   ne_tile<T, TX, TY, ZG, PRO, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
@@ -367,6 +369,7 @@ static void launch_ne_dom(const NEJob<T>& J, bool zg, bool pro, int tx, hipStrea
 template <class T>
 void launch_ne(const NEJob<T>& J, bool zg, bool pro, int tx, hipStream_t s) {
   if (J.L.dom == SMG_DOM_LSHAPE) launch_ne_dom<T, SMG_DOM_LSHAPE>(J, zg, pro, tx, s);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) launch_ne_dom<T, SMG_DOM_UNIONJACK>(J, zg, pro, tx, s);
   else launch_ne_dom<T, SMG_DOM_SQUARE>(J, zg, pro, tx, s);
 }
 template void launch_ne<double>(const NEJob<double>&, bool, bool, int, hipStream_t);
@@ -456,10 +459,10 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
         switch (rb) {
 #define SMG_ROW(RB)                                                              \
   case RB:                                                                       \
-    if (interior(4 * I + 0, b)) v[0] += pro_w<0, RB, T>(Z);                      \
-    if (interior(4 * I + 1, b)) v[1] += pro_w<1, RB, T>(Z);                      \
-    if (interior(4 * I + 2, b)) v[2] += pro_w<2, RB, T>(Z);                      \
-    if (interior(4 * I + 3, b)) v[3] += pro_w<3, RB, T>(Z);                      \
+    if (interior(4 * I + 0, b)) v[0] += sq_pro<0, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 1, b)) v[1] += sq_pro<1, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 2, b)) v[2] += sq_pro<2, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 3, b)) v[3] += sq_pro<3, RB, T, DOM>(Nc, I, Jc, Z);    \
     break;
           SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
 #undef SMG_ROW
@@ -469,7 +472,7 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
       }
       for (int e = tid; e < PW4 * PH4; e += NT) {
         const int i = i0 - 4 + e % PW4, j = j0 - 4 + e / PW4;
-        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] + pro_p1(J.zp, N / 2, i, j) : T(0);
+        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] + sq_pro_p1<T, DOM>(J.zp, N / 2, i, j) : T(0);
       }
     } else {
       for (int e = tid; e < W4 * H4; e += NT) {
@@ -493,13 +496,17 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   for (int e = tid; e < (TX + 6) * (TY + 6); e += NT) {
     const int ci = e % (TX + 6), cj = e / (TX + 6);
     const int i = i0 - 3 + ci, j = j0 - 3 + cj;
-    T y[9];
-    if constexpr (ZG) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) y[k] = T(0);
-    } else {
-      cell_apply<T, true, true, H4, W4, PW4>(J.L, sx0, 2 * ci + 2, 2 * cj + 2, sx0p, ci + 1, cj + 1, y);
-    }
+    T y[9], ad[4];
+    auto UA = [&](int c, int da, int db) -> T {
+      if constexpr (ZG) return T(0);
+      else return sx0[c][2 * cj + 2 + db][2 * ci + 2 + da];
+    };
+    auto PA = [&](int di, int dj) -> T {
+      if constexpr (ZG) return T(0);
+      else return sx0p[(cj + 1 + dj) * PW4 + (ci + 1 + di)];
+    };
+    if constexpr (ZG) sq_rows<T, false, false, DOM>(J.L, i, j, UA, PA, y, ad);
+    else sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
       const int DA = cls & 1, DB = cls >> 1;
@@ -507,7 +514,7 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const T r = sf[c][2 * cj + DB][2 * ci + DA] - y[2 * cls + c];
-        sy[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+        sy[c][2 * cj + DB][2 * ci + DA] = in ? ad[cls] * r : T(0);
       }
     }
     const int q = cj * PW3 + ci;
@@ -519,13 +526,17 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   for (int e = tid; e < (TX + 4) * (TY + 4); e += NT) {
     const int ci = e % (TX + 4), cj = e / (TX + 4);
     const int i = i0 - 2 + ci, j = j0 - 2 + cj;
-    T z[9];
-    cell_apply<T, true, true, H3, W3, PW3>(J.L, sy, 2 * ci + 2, 2 * cj + 2, syp, ci + 1, cj + 1, z);
+    T z[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sy[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return syp[(cj + 1 + dj) * PW3 + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, z, ad);
+    }
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
       const int DA = cls & 1, DB = cls >> 1;
       const bool in = interior(2 * i + DA, 2 * j + DB);
-      const T d = J.L.adinv[cls] * tau;
+      const T d = ad[cls] * tau;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         T x0 = T(0);
@@ -544,8 +555,12 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
     const int ci = e % (TX + 2), cj = e / (TX + 2);
     const int i = i0 - 1 + ci, j = j0 - 1 + cj;
-    T y[9];
-    cell_apply<T, true, true, H2, W2, PW2>(J.L, sx1, 2 * ci + 2, 2 * cj + 2, sx1p, ci + 1, cj + 1, y);
+    T y[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sx1[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return sx1p[(cj + 1 + dj) * PW2 + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
+    }
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
       const int DA = cls & 1, DB = cls >> 1;
@@ -553,7 +568,7 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const T r = sf[c][2 * cj + 4 + DB][2 * ci + 4 + DA] - y[2 * cls + c];
-        sy2[c][2 * cj + DB][2 * ci + DA] = in ? J.L.adinv[cls] * r : T(0);
+        sy2[c][2 * cj + DB][2 * ci + DA] = in ? ad[cls] * r : T(0);
       }
     }
     const int q3 = (cj + 2) * PW3 + ci + 2;
@@ -569,36 +584,30 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
     if (i <= N && j <= N) {
       auto UA = [&](int c, int da, int db) -> T { return sy2[c][2 * ty + 2 + db][2 * tx + 2 + da]; };
       auto PA = [&](int di, int dj) -> T { return syp[(ty + 1 + dj) * PW1 + (tx + 1 + di)]; };
-      auto emit = [&](int cls, T z0, T z1) {
+      auto emit = [&](int cls, T z0, T z1, T ad) {
         const int DA = cls & 1, DB = cls >> 1;
         const int a = 2 * i + DA, b = 2 * j + DB;
         if (a > 2 * N || b > 2 * N) return;
         const bool in = interior(a, b);
         const size_t g = (size_t)b * M + a;
-        const T d = J.L.adinv[cls] * tau;
+        const T d = ad * tau;
         J.ou[g] = in ? sx1[0][2 * ty + 4 + DB][2 * tx + 4 + DA] + d * z0 : T(0);
         J.ou[(size_t)M * M + g] = in ? sx1[1][2 * ty + 4 + DB][2 * tx + 4 + DA] + d * z1 : T(0);
       };
-      T z0, z1;
+      T z0, z1, ad;
       if (part == 0) {
-        auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, db); };
-        cell_vel<0, T, true, true>(J.L, Uc, PA, z0, z1);
-        emit(0, z0, z1);
+        sq_vel<0, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(0, z0, z1, ad);
       } else if (part == 1) {
-        auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, db); };
-        cell_vel<1, T, true, true>(J.L, Uc, PA, z0, z1);
-        emit(1, z0, z1);
+        sq_vel<1, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(1, z0, z1, ad);
       } else if (part == 2) {
-        auto Uc = [&](int c, int da, int db) -> T { return UA(c, da, 1 + db); };
-        cell_vel<2, T, true, true>(J.L, Uc, PA, z0, z1);
-        emit(2, z0, z1);
+        sq_vel<2, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(2, z0, z1, ad);
       } else {
-        auto Uc = [&](int c, int da, int db) -> T { return UA(c, 1 + da, 1 + db); };
-        cell_vel<3, T, true, true>(J.L, Uc, PA, z0, z1);
-        emit(3, z0, z1);
-        auto U0 = [&](int da, int db) -> T { return UA(0, da, db); };
-        auto U1 = [&](int da, int db) -> T { return UA(1, da, db); };
-        const T zp = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+        sq_vel<3, T, true, true, DOM>(J.L, i, j, UA, PA, z0, z1, ad);
+        emit(3, z0, z1, ad);
+        const T zp = sq_prow<T, DOM>(J.L, i, j, UA);
         J.op[(size_t)j * NP + i] = sx1p[(ty + 2) * PW2 + tx + 2] + tau * ss[(ty + 3) * PW3 + tx + 3] * zp;
       }
     }
@@ -628,6 +637,7 @@ static void launch_ne2_dom(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) 
 template <class T>
 void launch_ne2(const NEJob<T>& J, bool zg, bool pro, hipStream_t s) {
   if (J.L.dom == SMG_DOM_LSHAPE) launch_ne2_dom<T, SMG_DOM_LSHAPE>(J, zg, pro, s);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) launch_ne2_dom<T, SMG_DOM_UNIONJACK>(J, zg, pro, s);
   else launch_ne2_dom<T, SMG_DOM_SQUARE>(J, zg, pro, s);
 }
 template void launch_ne2<double>(const NEJob<double>&, bool, bool, hipStream_t);
@@ -726,18 +736,16 @@ __device__ __forceinline__ void uz_tile(const UZJob<T>& J, int tile) {
 
   // ---- step 1: u' on the tile plus two squares
   if (act1) {
-    T y[9];
-    if constexpr (ZG) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) y[k] = T(0);
-    } else {
-      cell_apply<T, true, true, XH, XW, PW>(J.L, sx, 2 * c1i + 2, 2 * c1j + 2, sxp, c1i + 1, c1j + 1, y);
-    }
+    T y[9], ad[4];
+    auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * c1j + 2 + db][2 * c1i + 2 + da]; };
+    auto PA = [&](int di, int dj) -> T { return sxp[(c1j + 1 + dj) * PW + (c1i + 1 + di)]; };
+    if constexpr (ZG) sq_rows<T, false, false, DOM>(J.L, s1i, s1j, UA, PA, y, ad);
+    else sq_rows<T, true, true, DOM>(J.L, s1i, s1j, UA, PA, y, ad);
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
       const int DA = cls & 1, DB = cls >> 1;
       const bool in = interior(2 * s1i + DA, 2 * s1j + DB);
-      const T d = J.tau * J.L.adinv[cls];
+      const T d = J.tau * ad[cls];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         T x0 = T(0);
@@ -750,9 +758,8 @@ __device__ __forceinline__ void uz_tile(const UZJob<T>& J, int tile) {
 
   // ---- step 2: dp on the tile's vertices plus one
   if (tid < DW * DH) {
-    auto U0 = [&](int da, int db) -> T { return sh[0][2 * v2j + 2 + db][2 * v2i + 2 + da]; };
-    auto U1 = [&](int da, int db) -> T { return sh[1][2 * v2j + 2 + db][2 * v2i + 2 + da]; };
-    const T bu = J.L.h * (SMG_BX_ROW(U0) + SMG_BY_ROW(U1));
+    auto UH = [&](int c, int da, int db) -> T { return sh[c][2 * v2j + 2 + db][2 * v2i + 2 + da]; };
+    const T bu = sq_prow<T, DOM>(J.L, vi, vj, UH);
     sd[tid] = act2 ? -J.sigma * s2 * (g2 - bu) : T(0);
   }
   __syncthreads();
@@ -765,27 +772,27 @@ __device__ __forceinline__ void uz_tile(const UZJob<T>& J, int tile) {
     if (i <= N && j <= N) {
       auto PA = [&](int di, int dj) -> T { return sd[(ty + 1 + dj) * DW + (tx + 1 + di)]; };
       auto Un = [&](int c, int da, int db) -> T { return T(0); };
-      auto emit = [&](int cls, T z0, T z1) {
+      auto emit = [&](int cls, T z0, T z1, T ad) {
         const int DA = cls & 1, DB = cls >> 1;
         const int a = 2 * i + DA, b = 2 * j + DB;
         if (a > 2 * N || b > 2 * N) return;
         const bool in = interior(a, b);
         const size_t g = (size_t)b * M + a;
-        const T d = J.tau * J.L.adinv[cls];
+        const T d = J.tau * ad;
         J.ou[g] = in ? sh[0][2 * ty + 4 + DB][2 * tx + 4 + DA] - d * z0 : T(0);
         J.ou[(size_t)M * M + g] = in ? sh[1][2 * ty + 4 + DB][2 * tx + 4 + DA] - d * z1 : T(0);
       };
-      T z0, z1;
+      T z0, z1, ad;
       if (part == 0) {
-        cell_vel<0, T, false, true>(J.L, Un, PA, z0, z1);
-        emit(0, z0, z1);
-        cell_vel<1, T, false, true>(J.L, Un, PA, z0, z1);
-        emit(1, z0, z1);
+        sq_vel<0, T, false, true, DOM>(J.L, i, j, Un, PA, z0, z1, ad);
+        emit(0, z0, z1, ad);
+        sq_vel<1, T, false, true, DOM>(J.L, i, j, Un, PA, z0, z1, ad);
+        emit(1, z0, z1, ad);
       } else {
-        cell_vel<2, T, false, true>(J.L, Un, PA, z0, z1);
-        emit(2, z0, z1);
-        cell_vel<3, T, false, true>(J.L, Un, PA, z0, z1);
-        emit(3, z0, z1);
+        sq_vel<2, T, false, true, DOM>(J.L, i, j, Un, PA, z0, z1, ad);
+        emit(2, z0, z1, ad);
+        sq_vel<3, T, false, true, DOM>(J.L, i, j, Un, PA, z0, z1, ad);
+        emit(3, z0, z1, ad);
         T p0 = T(0);
         if constexpr (!ZG) p0 = sxp[(ty + 3) * PW + tx + 3];
         J.op[(size_t)j * NP + i] = dom_p(N, DOM, i, j) ? p0 + PA(0, 0) : T(0);
@@ -818,6 +825,7 @@ static void launch_uz_dom(const UZJob<T>& J, bool zg, hipStream_t s) {
 template <class T>
 void launch_uz(const UZJob<T>& J, bool zg, hipStream_t s) {
   if (J.L.dom == SMG_DOM_LSHAPE) launch_uz_dom<T, SMG_DOM_LSHAPE>(J, zg, s);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) launch_uz_dom<T, SMG_DOM_UNIONJACK>(J, zg, s);
   else launch_uz_dom<T, SMG_DOM_SQUARE>(J, zg, s);
 }
 template void launch_uz<double>(const UZJob<double>&, bool, hipStream_t);
@@ -906,8 +914,12 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     if (e >= NC1 * NC1) break;
     const int ci = e % NC1, cj = e / NC1;
     const int i = 2 * I0 - 2 + ci, j = 2 * J0 - 2 + cj;
-    T y[9];
-    cell_apply<T, true, true, XW, XW, XPW>(J.L, sx, 2 * ci + 2, 2 * cj + 2, sxp, ci + 1, cj + 1, y);
+    T y[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return sxp[(cj + 1 + dj) * XPW + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
+    }
 #pragma unroll
     for (int cls = 0; cls < 4; ++cls) {
       const int DA = cls & 1, DB = cls >> 1;
@@ -936,10 +948,10 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
         T v = T(0);
         if (in) {
           switch (cls) {
-            case 0: v = cell_res<0, T>(R); break;
-            case 1: v = cell_res<1, T>(R); break;
-            case 2: v = cell_res<2, T>(R); break;
-            default: v = cell_res<3, T>(R); break;
+            case 0: v = sq_res<0, T, DOM>(Nc, I, Jc, R); break;
+            case 1: v = sq_res<1, T, DOM>(Nc, I, Jc, R); break;
+            case 2: v = sq_res<2, T, DOM>(Nc, I, Jc, R); break;
+            default: v = sq_res<3, T, DOM>(Nc, I, Jc, R); break;
           }
         }
         J.cu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] = v;
@@ -947,10 +959,7 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     }
     if (cls == 3) {
       auto Rp = [&](int di, int dj) -> T { return srp[(2 * ty + 2 + dj) * RPW + (2 * tx + 2 + di)]; };
-      J.cp[(size_t)Jc * NPc + I] =
-          dom_p(Nc, DOM, I, Jc)
-              ? Rp(0, 0) + T(0.5) * (Rp(1, 0) + Rp(-1, 0) + Rp(0, 1) + Rp(0, -1) + Rp(1, 1) + Rp(-1, -1))
-              : T(0);
+      J.cp[(size_t)Jc * NPc + I] = dom_p(Nc, DOM, I, Jc) ? sq_resp<T, DOM>(Nc, I, Jc, Rp) : T(0);
     }
   }
 }
@@ -986,6 +995,7 @@ void launch_resid_restrict(const RRJob<T>& J, hipStream_t s) {
   const int Nc = J.L.N / 2;
   const int nb = ((Nc + 8) / 8) * ((Nc + 8) / 8);
   if (J.L.dom == SMG_DOM_LSHAPE) k_resid_restrict<T, SMG_DOM_LSHAPE><<<nb, 256, 0, s>>>(J);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) k_resid_restrict<T, SMG_DOM_UNIONJACK><<<nb, 256, 0, s>>>(J);
   else k_resid_restrict<T, SMG_DOM_SQUARE><<<nb, 256, 0, s>>>(J);
 }
 template void launch_resid_restrict<double>(const RRJob<double>&, hipStream_t);

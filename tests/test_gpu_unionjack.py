@@ -153,13 +153,14 @@ def _params(kind):
             "uzawa_w33": (dict(smoother="uzawa", nu_pre=3, nu_post=3, gamma=2), mg.Params.uzawa(gamma=2))}[kind]
 
 
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
 @pytest.mark.parametrize("kind", ["ne", "ne_w33", "uzawa_w33"])
 @pytest.mark.parametrize("N,beta", [(8, 1.0), (32, 1e4), (64, 0.0), (128, 1e8)])
-def test_iterates_on_union_jack(kind, N, beta):
-    print(f"union-jack cycle {kind} N={N} beta={beta}", flush=True)
+def test_iterates_on_union_jack(kind, N, beta, fused):
+    print(f"union-jack cycle {kind} N={N} beta={beta} fused={fused}", flush=True)
     gkw, prm = _params(kind)
     oh = oracle_uj(N, beta)
-    gh = gpu_uj(N, beta, **gkw)
+    gh = gpu_uj(N, beta, fused=fused, **gkw)
     F, G = inputs.normal_fg(N, seed=21)
     f, FU, GP = _rhs(oh, F, G)
     FU, GP = dev(FU), dev(GP)
@@ -175,7 +176,8 @@ def test_iterates_on_union_jack(kind, N, beta):
 
 def test_solve_on_union_jack():
     """h = 1/128, f iid U[-1,1] (seed 0), g = 0, NE V(2,2) to 1e-8: the
-    oracle's iterate count and solution."""
+    oracle's iterate count and solution; FP32 cycles in FP64 refinement reach
+    1e-10 in the oracle's residual."""
     N, beta = 128, 1e2
     oh = oracle_uj(N, beta)
     gh = gpu_uj(N, beta)
@@ -188,6 +190,10 @@ def test_solve_on_union_jack():
     assert info.iters == res.iters or (near and abs(info.iters - res.iters) == 1), (info.iters, res.iters)
     got = lat.from_lattice(oh.discs[-1], host(U), host(P))
     assert np.linalg.norm(got - res.x) <= PARITY * np.linalg.norm(res.x)
+    Um, Pm, im = gh.solve_mixed(dev(FU), dev(GP), rtol=1e-10, maxit=400)
+    assert im.status == "ok", im
+    xm = lat.from_lattice(oh.discs[-1], host(Um), host(Pm))
+    assert np.linalg.norm(f - oh.top.calA @ xm) <= 1.01e-10 * np.linalg.norm(f)
 
 
 _XSTAR = {}
