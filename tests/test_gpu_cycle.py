@@ -209,3 +209,23 @@ def test_incompatible_pressure_data_reported():
     B = Batch([N, N], [1.0, 1.0])
     _, _, infos = B.solve([fu, fu2], [gp, gp2], rtol=1e-8, maxit=300)
     assert [i.status for i in infos] == ["incompatible", "ok"], infos
+
+
+@pytest.mark.parametrize("kind", ["ne", "uzawa"])
+def test_error_protocol_on_square_matches_oracle(kind):
+    """The Section 6 measurement protocol (f = calA x*, stop at 1e-9 reduction
+    of the L-norm error) on the same-diagonal grid, h = 1/32, x* random: the
+    oracle's iterate count and mean rate."""
+    N, beta = 32, 1e2
+    gkw, prm = _params(kind)
+    oh = oracle_level(N, beta, 2)
+    gh = gpu_hier(N, beta, **gkw)
+    d = oh.discs[-1]
+    xs = oh.top.project_mean(np.random.default_rng(5).standard_normal(oh.top.n))
+    us, ps = lat.to_lattice(d, xs)
+    Us, Ps = dev(us), dev(ps)
+    FU, GP = gh.apply(Us, Ps)
+    _, _, n, q, st = gh.solve_error(FU, GP, Us, Ps, eps=1e-9, maxit=200)
+    n_o, q_o = mg.error_reduction_run(oh, xs, prm, eps=1e-9, maxit=200)
+    assert st == "ok" and n_o is not None
+    assert abs(n - n_o) <= 1 and abs(q - q_o) <= 1e-3 * q_o, (n, n_o, q, q_o)
