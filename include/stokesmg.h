@@ -104,8 +104,7 @@ typedef struct {
                        SMG_DOMAIN_UNIONJACK: the unit square on the grid of the
                        experiments of Section 6 (the coarsest 2 x 2 grid with
                        the diagonals meeting at the centre, refined
-                       uniformly); needs an even n0; single hierarchies only
-                       (no batches).                                           */
+                       uniformly); needs an even n0.                           */
 } smg_params;
 
 enum { SMG_DOMAIN_SQUARE = 0, SMG_DOMAIN_LSHAPE = 1, SMG_DOMAIN_UNIONJACK = 2 };

@@ -297,8 +297,7 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
 // The domain is a template parameter of every fused kernel (chosen by the
 // host launchers): a run-time test would cost the square's kernels a few
 // percent, and two instantiations inside one kernel would double its static
-// LDS.  The single-instance launchers cover all three grids; the batched ones
-// the square and the L-shape (batches reject the union-jack grid).
+// LDS.
 template <class T, int TX, int TY, bool ZG, bool PRO, int DOM>
 __global__ __launch_bounds__(2 * TX* TY) void k_ne(NEJob<T> J) {
   ne_tile<T, TX, TY, ZG, PRO, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
@@ -332,6 +331,7 @@ static void launch_ne_b_dom(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, 
 template <class T>
 void launch_ne_b(const JobArg<NEJob<T>>& A, int nb, int tx, bool zg, bool pro, int dom, hipStream_t s) {
   if (dom == SMG_DOM_LSHAPE) launch_ne_b_dom<T, SMG_DOM_LSHAPE>(A, nb, tx, zg, pro, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_ne_b_dom<T, SMG_DOM_UNIONJACK>(A, nb, tx, zg, pro, s);
   else launch_ne_b_dom<T, SMG_DOM_SQUARE>(A, nb, tx, zg, pro, s);
 }
 template void launch_ne_b<double>(const JobArg<NEJob<double>>&, int, int, bool, bool, int, hipStream_t);
@@ -659,6 +659,7 @@ static void launch_ne2_b_dom(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pr
 template <class T>
 void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zg, bool pro, int dom, hipStream_t s) {
   if (dom == SMG_DOM_LSHAPE) launch_ne2_b_dom<T, SMG_DOM_LSHAPE>(A, nb, zg, pro, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_ne2_b_dom<T, SMG_DOM_UNIONJACK>(A, nb, zg, pro, s);
   else launch_ne2_b_dom<T, SMG_DOM_SQUARE>(A, nb, zg, pro, s);
 }
 template void launch_ne2_b<double>(const JobArg<NEJob<double>>&, int, bool, bool, int, hipStream_t);
@@ -845,6 +846,7 @@ static void launch_uz_b_dom(const JobArg<UZJob<T>>& A, int nb, bool zg, hipStrea
 template <class T>
 void launch_uz_b(const JobArg<UZJob<T>>& A, int nb, bool zg, int dom, hipStream_t s) {
   if (dom == SMG_DOM_LSHAPE) launch_uz_b_dom<T, SMG_DOM_LSHAPE>(A, nb, zg, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_uz_b_dom<T, SMG_DOM_UNIONJACK>(A, nb, zg, s);
   else launch_uz_b_dom<T, SMG_DOM_SQUARE>(A, nb, zg, s);
 }
 template void launch_uz_b<double>(const JobArg<UZJob<double>>&, int, bool, int, hipStream_t);
@@ -985,6 +987,7 @@ static void launch_rr_b_dom(const JobArg<RRJob<T>>& A, int nb, hipStream_t s) {
 template <class T>
 void launch_rr_b(const JobArg<RRJob<T>>& A, int nb, int dom, hipStream_t s) {
   if (dom == SMG_DOM_LSHAPE) launch_rr_b_dom<T, SMG_DOM_LSHAPE>(A, nb, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_rr_b_dom<T, SMG_DOM_UNIONJACK>(A, nb, s);
   else launch_rr_b_dom<T, SMG_DOM_SQUARE>(A, nb, s);
 }
 template void launch_rr_b<double>(const JobArg<RRJob<double>>&, int, int, hipStream_t);
@@ -1034,6 +1037,7 @@ __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T
 template <class T>
 void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, int dom, hipStream_t s) {
   if (dom == SMG_DOM_LSHAPE) k_coarse_cycle_b<T, SMG_DOM_LSHAPE><<<njobs, CC_THREADS, lds, s>>>(jobs);
+  else if (dom == SMG_DOM_UNIONJACK) k_coarse_cycle_b<T, SMG_DOM_UNIONJACK><<<njobs, CC_THREADS, lds, s>>>(jobs);
   else k_coarse_cycle_b<T, SMG_DOM_SQUARE><<<njobs, CC_THREADS, lds, s>>>(jobs);
 }
 template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, int, hipStream_t);
@@ -1061,11 +1065,12 @@ template int launch_coarse_cycle<float>(const CoarseJob<float>&, hipStream_t);
 
 template <class T>
 int coarse_cycle_allow_lds(size_t bytes) {
-  const void* fns[5] = {(const void*)k_coarse_cycle<T, SMG_DOM_SQUARE>,
+  const void* fns[6] = {(const void*)k_coarse_cycle<T, SMG_DOM_SQUARE>,
                         (const void*)k_coarse_cycle_b<T, SMG_DOM_SQUARE>,
                         (const void*)k_coarse_cycle<T, SMG_DOM_LSHAPE>,
                         (const void*)k_coarse_cycle_b<T, SMG_DOM_LSHAPE>,
-                        (const void*)k_coarse_cycle<T, SMG_DOM_UNIONJACK>};
+                        (const void*)k_coarse_cycle<T, SMG_DOM_UNIONJACK>,
+                        (const void*)k_coarse_cycle_b<T, SMG_DOM_UNIONJACK>};
   for (const void* f : fns) {
     const int e = (int)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != 0) return e;

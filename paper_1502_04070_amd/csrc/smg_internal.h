@@ -142,7 +142,7 @@ unsigned stencil_flags(const StencilJob<T>& J, int rows);
 // batched: jobs with identical flags, one tile shape (tx, ty) for all
 template <class T>
 void launch_stencil_b(const JobArg<StencilJob<T>>& A, int nb, int tx, int ty,
-                      unsigned flags, hipStream_t s);
+                      unsigned flags, int dom, hipStream_t s);
 int stencil_tiles_shape(int N, int tx, int ty);
 
 // batched prolongation (one job per instance)

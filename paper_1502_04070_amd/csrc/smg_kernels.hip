@@ -386,8 +386,22 @@ __global__ __launch_bounds__(TX* TY) void k_stencil_b(const JobArg<StencilJob<T>
   stencil_tile<T, TX, TY, F, -1>(J, tile);
 }
 
+// union-jack grid, batched: the generic kernel with the rows summed square by square
+template <class T, int TX, int TY, bool PACK>
+__global__ __launch_bounds__(TX* TY) void k_stencil_uj_b(const JobArg<StencilJob<T>> A) {
+  int tile;
+  const StencilJob<T> J = block_job<PACK>(A, xcd_swizzle(blockIdx.x, gridDim.x), tile);
+  if (J.done && *J.done) return;
+  stencil_tile<T, TX, TY, 0u, SMG_DOM_UNIONJACK>(J, tile);
+}
+
 template <class T, int TX, int TY>
-static void launch_stencil_b_shape(const JobArg<StencilJob<T>>& A, int nb, unsigned f, hipStream_t s) {
+static void launch_stencil_b_shape(const JobArg<StencilJob<T>>& A, int nb, unsigned f, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_UNIONJACK) {
+    if (A.n > 0) k_stencil_uj_b<T, TX, TY, true><<<nb, TX * TY, 0, s>>>(A);
+    else k_stencil_uj_b<T, TX, TY, false><<<nb, TX * TY, 0, s>>>(A);
+    return;
+  }
 #define SMG_CASE(MODE)                                                          \
   case MODE:                                                                    \
     if (A.n > 0) k_stencil_b<T, TX, TY, MODE, true><<<nb, TX * TY, 0, s>>>(A);  \
@@ -408,15 +422,16 @@ static void launch_stencil_b_shape(const JobArg<StencilJob<T>>& A, int nb, unsig
 }
 
 template <class T>
-void launch_stencil_b(const JobArg<StencilJob<T>>& A, int nb, int tx, int ty, unsigned flags,
+void launch_stencil_b(const JobArg<StencilJob<T>>& A, int nb, int tx, int ty, unsigned flags, int dom,
                       hipStream_t s) {
-  if (tx == 16 && ty == 16) launch_stencil_b_shape<T, 16, 16>(A, nb, flags, s);
-  else if (tx == 16 && ty == 8) launch_stencil_b_shape<T, 16, 8>(A, nb, flags, s);
-  else launch_stencil_b_shape<T, 8, 8>(A, nb, flags, s);
+  if (tx == 16 && ty == 16) launch_stencil_b_shape<T, 16, 16>(A, nb, flags, dom, s);
+  else if (tx == 16 && ty == 8) launch_stencil_b_shape<T, 16, 8>(A, nb, flags, dom, s);
+  else launch_stencil_b_shape<T, 8, 8>(A, nb, flags, dom, s);
 }
-template void launch_stencil_b<double>(const JobArg<StencilJob<double>>&, int, int, int, unsigned,
+template void launch_stencil_b<double>(const JobArg<StencilJob<double>>&, int, int, int, unsigned, int,
                                        hipStream_t);
-template void launch_stencil_b<float>(const JobArg<StencilJob<float>>&, int, int, int, unsigned, hipStream_t);
+template void launch_stencil_b<float>(const JobArg<StencilJob<float>>&, int, int, int, unsigned, int,
+                                      hipStream_t);
 
 // ---------------------------------------------------------------------------
 // transfers (Section 3): one thread per coarse square
@@ -609,13 +624,18 @@ __global__ __launch_bounds__(256) void k_prolong_add(int Nc, int dom, const T* _
 
 int prolong_tiles(int Nc) { return ((Nc + 16) / 16) * ((Nc + 16) / 16); }
 
+template <class T>
+__device__ __forceinline__ void prolong_uj_body(int Nc, const T* __restrict__ zu, const T* __restrict__ zp,
+                                                T* u, T* p, int bx, int by);
+
 template <class T, bool PACK>
 __global__ __launch_bounds__(256) void k_prolong_b(const JobArg<ProJob<T>> A) {
   int tile;
   const ProJob<T> J = block_job<PACK>(A, (int)blockIdx.x, tile);
   if (J.done && *J.done) return;
   const int ntx = (J.Nc + 16) / 16;
-  prolong_body<T>(J.Nc, J.dom, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
+  if (J.dom == SMG_DOM_UNIONJACK) prolong_uj_body<T>(J.Nc, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
+  else prolong_body<T>(J.Nc, J.dom, J.zu, J.zp, J.u, J.p, tile % ntx, tile / ntx);
 }
 
 template <class T>
@@ -629,13 +649,11 @@ template void launch_prolong_b<float>(const JobArg<ProJob<float>>&, int, hipStre
 // Union-jack grid: every coarse square adds the interpolant of its coarse
 // nodes at the fine points it owns, with the table of its diagonal direction.
 template <class T>
-__global__ __launch_bounds__(256) void k_prolong_uj(int Nc, const T* __restrict__ zu,
-                                                    const T* __restrict__ zp, T* u, T* p,
-                                                    const int* done) {
+__device__ __forceinline__ void prolong_uj_body(int Nc, const T* __restrict__ zu, const T* __restrict__ zp,
+                                                T* u, T* p, int bx, int by) {
   using namespace smg_stencil;
-  if (done && *done) return;
-  const int I = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int J = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int I = bx * 16 + (threadIdx.x & 15);
+  const int J = by * 16 + (threadIdx.x >> 4);
   if (I > Nc || J > Nc) return;
   const int Nf = 2 * Nc, Mc = 2 * Nc + 1, Mf = 2 * Nf + 1, NPc = Nc + 1, NPf = Nf + 1;
   const int o = uj_orient_c(Nc, I, J);
@@ -665,6 +683,14 @@ __global__ __launch_bounds__(256) void k_prolong_uj(int Nc, const T* __restrict_
     for (int q = 0; q < 4; ++q) w += T(UJ_PP[o][v][q]) * zc[q];
     p[(size_t)fj * NPf + fi] += w;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_uj(int Nc, const T* __restrict__ zu,
+                                                    const T* __restrict__ zp, T* u, T* p,
+                                                    const int* done) {
+  if (done && *done) return;
+  prolong_uj_body<T>(Nc, zu, zp, u, p, blockIdx.x, blockIdx.y);
 }
 
 template <class T>

@@ -279,3 +279,46 @@ def test_tables_2_3_on_gpu_against_paper(k):
             _, _, n, q, st = gh.solve_error(FU, GP, Us, Ps)
             n_paper = GOLD[table][row][ib][0]
             assert st == "ok" and _band(n, n_paper), (kind, k, beta, n, n_paper)
+
+
+@pytest.mark.parametrize("kind", ["ne", "uzawa_w33"])
+def test_batch_on_union_jack(kind):
+    """Uneven union-jack instances (h = 1/8 ... 1/128) in one batch, FP64 and
+    mixed: each equals its own single-instance solve (same count, solution to
+    1e-10), the h = 1/64 one equals the oracle's solve, and the mixed solves
+    reach 1e-10 in the oracle's residual."""
+    from paper_1502_04070_amd.solver import Batch
+    gkw, prm = _params(kind)
+    Ns, betas = [8, 64, 128, 32, 64], [1.0, 1e3, 0.5, 1e4, 20.0]
+    print(f"union-jack batch {kind} Ns={Ns}", flush=True)
+    B = Batch(Ns, betas, domain="union_jack", **gkw)
+    fus, gps, fs = [], [], []
+    for k, N in enumerate(Ns):
+        F, G = inputs.normal_fg(N, seed=70 + k)
+        f, FU, GP = _rhs(oracle_uj(N, betas[k]), F, G)
+        fus.append(dev(FU))
+        gps.append(dev(GP))
+        fs.append(f)
+    us, ps, infos = B.solve(fus, gps, rtol=1e-9, maxit=300)
+    for k, N in enumerate(Ns):
+        assert infos[k].status == "ok", (k, infos[k])
+        U, P, info = gpu_uj(N, betas[k], **gkw).solve(fus[k], gps[k], rtol=1e-9, maxit=300)
+        assert abs(info.iters - infos[k].iters) <= 1, (k, info.iters, infos[k].iters)
+        if info.iters == infos[k].iters:
+            d = oracle_uj(N, betas[k]).discs[-1]
+            a = lat.from_lattice(d, host(us[k]), host(ps[k]))
+            b = lat.from_lattice(d, host(U), host(P))
+            assert np.linalg.norm(a - b) <= PARITY * np.linalg.norm(b), k
+    k = 1
+    oh = oracle_uj(Ns[k], betas[k])
+    res = mg.solve(oh, fs[k], prm, tol=1e-9, maxit=300)
+    assert abs(res.iters - infos[k].iters) <= 1, (res.iters, infos[k].iters)
+    if res.iters == infos[k].iters:
+        got = lat.from_lattice(oh.discs[-1], host(us[k]), host(ps[k]))
+        assert np.linalg.norm(got - res.x) <= PARITY * np.linalg.norm(res.x)
+    um, pm, im = B.solve_mixed(fus, gps, rtol=1e-10, maxit=400)
+    for k, N in enumerate(Ns):
+        oh = oracle_uj(N, betas[k])
+        assert im[k].status == "ok", (k, im[k])
+        x = lat.from_lattice(oh.discs[-1], host(um[k]), host(pm[k]))
+        assert np.linalg.norm(fs[k] - oh.top.calA @ x) <= 1.01e-10 * np.linalg.norm(fs[k]), k
