@@ -1012,30 +1012,24 @@ template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
 // FP64 stencil rows without spills
 constexpr int CC_THREADS = 768;
 
-// The job (about 1.4 KB of coefficients and pointers) is staged in LDS once.
-// Read from the kernel arguments, every per-level coefficient would be a
-// scalar load, whose wait also drains the LDS reads in flight (both count on
-// one counter); read through global memory, a vector load.
-template <class T>
-__device__ __forceinline__ void cc_stage_job(const CoarseJob<T>* src_job, CoarseJob<T>& sj) {
-  const unsigned* src = reinterpret_cast<const unsigned*>(src_job);
-  unsigned* dst = reinterpret_cast<unsigned*>(&sj);
-  for (int e = threadIdx.x; e < (int)(sizeof(CoarseJob<T>) / 4); e += blockDim.x) dst[e] = src[e];
-  __syncthreads();
-}
-
 template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle(CoarseJob<T> J) {
   if (J.done && *J.done) return;
-  __shared__ CoarseJob<T> sj;
-  cc_stage_job<T>(&J, sj);
-  coarse_body<T, DOM>(sj);
+  coarse_body<T, DOM>(J);
 }
 
 template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T>* __restrict__ jobs) {
+  // the job (about 1.4 KB of coefficients and pointers) is staged in LDS once;
+  // read through global memory, every coefficient access inside the phases
+  // would be a vector load
   __shared__ CoarseJob<T> sj;
-  cc_stage_job<T>(jobs + blockIdx.x, sj);
+  {
+    const unsigned* src = reinterpret_cast<const unsigned*>(jobs + blockIdx.x);
+    unsigned* dst = reinterpret_cast<unsigned*>(&sj);
+    for (int e = threadIdx.x; e < (int)(sizeof(CoarseJob<T>) / 4); e += blockDim.x) dst[e] = src[e];
+  }
+  __syncthreads();
   if (sj.done && *sj.done) return;
   coarse_body<T, DOM>(sj);
 }
