@@ -107,3 +107,35 @@ def test_batched_gradients_match_single():
         for a, r in ((f.grad[k], fk.grad), (g.grad[k], gk.grad)):
             assert float((a - r).abs().max()) <= 1e-9 * float(r.abs().max())
         assert abs(float(b.grad[k]) - float(bk.grad)) <= 1e-9 * abs(float(bk.grad))
+
+
+@pytest.mark.parametrize("domain", ["l_shape", "union_jack"])
+def test_gradients_on_other_grids_match_oracle_adjoint(domain):
+    """The differentiable solve on the L-shape and on the union-jack grid
+    (h = 1/16, beta = 30): solution, dL/df, dL/dg and dL/dbeta equal the
+    oracle's adjoint on that grid (sparse direct solves) to 1e-8, for
+    L = 1/2 |u - u_t|^2 + w_p . p over the lattice (targets and weights zero
+    off the domain's unknowns)."""
+    from oracle import multigrid as mg
+    N, beta = 16, 30.0
+    oh = mg.Hierarchy(domain, int(round(np.log2(N // 2))), beta, n0=2)
+    lv, d = oh.top, oh.discs[-1]
+    rng = np.random.default_rng(70)
+    ut, wp = lat.to_lattice(d, rng.standard_normal(lv.n))
+    F, G = inputs.normal_fg(N, seed=71)
+    f = dev(F).requires_grad_(True)
+    g = dev(G).requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, device="cuda", requires_grad=True)
+    u, p = ag.stokes_solve(f, g, b, rtol=1e-13, domain=domain)
+    loss = 0.5 * ((u - dev(ut)) ** 2).sum() + (dev(wp) * p).sum()
+    loss.backward()
+    fn, gn = lat.lattice_to_nodal(d, F, G)
+    x = oadj.forward(lv, fn, gn)
+    got_x = lat.from_lattice(d, host(u), host(p))
+    assert np.linalg.norm(got_x - x) <= 1e-10 * np.linalg.norm(x)
+    tv = lat.from_lattice(d, ut, wp)
+    df, dg, dbeta = oadj.gradients(lv, x, x[: lv.nu2] - tv[: lv.nu2], tv[lv.nu2:])
+    gdf, gdg = lat.lattice_to_nodal(d, host(f.grad), host(g.grad))
+    assert np.abs(gdf - df).max() <= 1e-8 * np.abs(df).max()
+    assert np.abs(gdg - dg).max() <= 1e-8 * np.abs(dg).max()
+    assert abs(float(b.grad) - dbeta) <= 1e-8 * abs(dbeta)

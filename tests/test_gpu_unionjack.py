@@ -322,3 +322,27 @@ def test_batch_on_union_jack(kind):
         assert im[k].status == "ok", (k, im[k])
         x = lat.from_lattice(oh.discs[-1], host(um[k]), host(pm[k]))
         assert np.linalg.norm(fs[k] - oh.top.calA @ x) <= 1.01e-10 * np.linalg.norm(fs[k]), k
+
+
+def test_implicit_step_on_union_jack():
+    """Two implicit Euler steps (dt = 1e-2, h = 1/32) on the union-jack grid
+    from a random divergence-carrying start: each equals the oracle's direct
+    step."""
+    from oracle import timestep as ots
+    N, dt = 32, 1e-2
+    oh = oracle_uj(N, 1.0 / dt)
+    gh = gpu_uj(N, 1.0 / dt)
+    d, lv = oh.discs[-1], oh.top
+    F, G = inputs.normal_fg(N, seed=80)
+    fn, _ = lat.lattice_to_nodal(d, F, G)
+    u0, _ = inputs.random_state(N, seed=81)
+    x = lat.from_lattice(d, u0, np.zeros((N + 1, N + 1)))
+    U, P = dev(u0), dev(np.zeros((N + 1, N + 1)))
+    u = x[: lv.nu2]
+    for s in range(2):
+        info = gh.implicit_step(U, P, f_nodal=dev(F), rtol=1e-13, maxit=300)
+        assert info.status == "ok", info
+        xr = ots.step(lv, u, fn)
+        got = lat.from_lattice(d, host(U), host(P))
+        assert np.linalg.norm(got - xr) <= 1e-9 * np.linalg.norm(xr), s
+        u = xr[: lv.nu2]
