@@ -294,6 +294,48 @@ def extras():
     del B, fus, gps, us, ps
     torch.cuda.empty_cache()
 
+    # The same 256 solves as the shares of an 8-GPU run: independent instances
+    # need no communication, so each GPU gets a batch of its own, placed
+    # longest first by unknowns; every share is timed here as its own batch
+    # (the slowest share is the run's time, without gathering the results).
+    n_gpu = 8
+    order = sorted(range(len(Ns)), key=lambda k: (-dofs(Ns[k]), k))
+    load, shares = [0] * n_gpu, [[] for _ in range(n_gpu)]
+    for k in order:
+        g = min(range(n_gpu), key=lambda q: (load[q], q))
+        shares[g].append(k)
+        load[g] += dofs(Ns[k])
+    share_ms, share_its = [], []
+    for sh in shares:
+        Bs = Batch([Ns[k] for k in sh], [betas[k] for k in sh], schedule=sched)
+        fus, gps = [], []
+        for h, k in zip(Bs.instances, sh):
+            F, G = fg[k]
+            Gd = torch.from_numpy(G).cuda()
+            h.project_mean(Gd)
+            fu, gp = h.load(torch.from_numpy(F).cuda(), Gd)
+            fus.append(fu)
+            gps.append(gp)
+        outs = [h.zeros() for h in Bs.instances]
+
+        def run_share():
+            for u, p in outs:
+                u.zero_()
+                p.zero_()
+            return Bs.solve(fus, gps, rtol=1e-8, maxit=400, us=[u for u, _ in outs], ps=[p for _, p in outs])[2]
+        run_share()
+        infos, dt = _timed(run_share)
+        assert all(i.status == "ok" for i in infos)
+        share_ms.append(1e3 * dt)
+        share_its.append(int(sum(i.iters for i in infos)))
+        del Bs, fus, gps, outs
+    torch.cuda.empty_cache()
+    out["batch_64x4_shares_of_8_gpus"] = {
+        "rule": "longest first by unknowns", "solves_per_share": [len(sh) for sh in shares],
+        "unknowns_per_share": [int(v) for v in load], "iterates_per_share": share_its,
+        "fp64_time_to_tol_ms_per_share": share_ms, "slowest_share_ms": max(share_ms),
+        "one_gpu_whole_batch_ms": rec["fp64"]["time_to_tol_ms"]}
+
     # h = 1/512, FP64 against FP32 cycles in FP64 refinement, to 1e-10
     N = 512
     F, G = inputs.smooth_plus_noise(N, seed=0)
