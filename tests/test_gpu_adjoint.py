@@ -81,7 +81,8 @@ def test_gradients_match_central_differences():
     assert abs(fdb - float(b.grad)) <= 1e-5 * abs(float(b.grad)), (fdb, float(b.grad))
 
 
-def test_batched_gradients_match_single():
+@pytest.mark.parametrize("domain", ["square", "union_jack"])
+def test_batched_gradients_match_single(domain):
     N, nb = 32, 3
     betas = [1.0, 1e3, 1e5]
     fs, gs, uts = [], [], []
@@ -93,7 +94,7 @@ def test_batched_gradients_match_single():
     g = torch.stack([dev(a) for a in gs]).requires_grad_(True)
     b = torch.tensor(betas, dtype=torch.float64, device="cuda", requires_grad=True)
     ut = torch.stack([dev(a) for a in uts])
-    u, p = ag.batch_stokes_solve(f, g, b, rtol=1e-12)
+    u, p = ag.batch_stokes_solve(f, g, b, rtol=1e-12, domain=domain)
     e = u - ut
     loss = sum(0.5 * (e[k] * ag.mass_product(e[k], N)).sum() for k in range(nb))
     loss.backward()
@@ -101,7 +102,7 @@ def test_batched_gradients_match_single():
         fk = dev(fs[k]).requires_grad_(True)
         gk = dev(gs[k]).requires_grad_(True)
         bk = torch.tensor(betas[k], dtype=torch.float64, device="cuda", requires_grad=True)
-        uk, pk = ag.stokes_solve(fk, gk, bk, rtol=1e-12)
+        uk, pk = ag.stokes_solve(fk, gk, bk, rtol=1e-12, domain=domain)
         ek = uk - dev(uts[k])
         (0.5 * (ek * ag.mass_product(ek, N)).sum()).backward()
         for a, r in ((f.grad[k], fk.grad), (g.grad[k], gk.grad)):

@@ -55,12 +55,13 @@ def test_step_with_divergence_data_and_warm_start():
     assert i2.iters < i1.iters
 
 
-def test_batched_steps_match_single():
+@pytest.mark.parametrize("domain", ["square", "l_shape", "union_jack"])
+def test_batched_steps_match_single(domain):
     Ns, dts = [32, 64, 32], [1e-2, 1e-3, 1.0]
     u0s = [dev(inputs.random_state(N, seed=90 + k)[0]) for k, N in enumerate(Ns)]
     Fs = [dev(inputs.normal_fg(N, seed=95 + k, with_g=False)[0]) for k, N in enumerate(Ns)]
-    bt = BatchImplicitEuler(Ns, dts, u0s=u0s)
-    singles = [ImplicitEuler(N, dt, u0=u0) for N, dt, u0 in zip(Ns, dts, u0s)]
+    bt = BatchImplicitEuler(Ns, dts, u0s=u0s, domain=domain)
+    singles = [ImplicitEuler(N, dt, u0=u0, domain=domain) for N, dt, u0 in zip(Ns, dts, u0s)]
     for _ in range(3):
         binfo = bt.step(Fs, rtol=1e-12, maxit=300)
         for k, ts in enumerate(singles):
