@@ -1126,22 +1126,32 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   __shared__ double red[4];
   __shared__ double sh_mean;
   __shared__ int sh_last;
-  double s1 = 0.0, s2 = 0.0;
+  // every global read of the block is issued before the first reduction:
+  // both sets of tile partials and the block's part of p
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int k = threadIdx.x; k < np; k += 256) {
     s1 += mpart[2 * k];
     s2 += mpart[2 * k + 1];
+    s3 += rpart[k];
+  }
+  const int n = (N + 1) * (N + 1);
+  double pv[4];
+  bool in[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk * 1024 + k * 256 + threadIdx.x;
+    in[k] = e < n && dom_p(N, dom, e % (N + 1), e / (N + 1));
+    pv[k] = in[k] ? p[e] : 0.0;
   }
   const double t1 = wg_sum<256>(s1, red);
   __syncthreads();
   const double t2 = wg_sum<256>(s2, red);
   if (threadIdx.x == 0) sh_mean = t1 / t2;
   __syncthreads();
-  const int n = (N + 1) * (N + 1);
   const double m = sh_mean;
-  for (int k = 0; k < 4; ++k) {
-    const int e = blk * 1024 + k * 256 + threadIdx.x;
-    if (e < n && dom_p(N, dom, e % (N + 1), e / (N + 1))) p[e] -= m;
-  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (in[k]) p[blk * 1024 + k * 256 + threadIdx.x] = pv[k] - m;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -1150,9 +1160,7 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   }
   __syncthreads();
   if (!sh_last) return;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < np; k += 256) s += rpart[k];
-  const double r2 = wg_sum<256>(s, red);
+  const double r2 = wg_sum<256>(s3, red);
   if (threadIdx.x == 0) {
     const double rel = sqrt(r2 / st->fnorm2);
     const int it = st->iters + 1;
