@@ -375,10 +375,10 @@ def extras():
         with torch.no_grad():
             return ag.batch_stokes_solve(fb, gz, bt, rtol=1e-10, maxit=500)
 
-    def forward_backward():
+    def forward_backward(mixed=False):
         f = fb.clone().requires_grad_(True)
         b = bt.clone().requires_grad_(True)
-        u, _ = ag.batch_stokes_solve(f, gz, b, rtol=1e-10, maxit=500)
+        u, _ = ag.batch_stokes_solve(f, gz, b, rtol=1e-10, maxit=500, mixed=mixed)
         e = u - ut
         loss = 0.5 * sum((e[k] * ag.mass_product(e[k], N)).sum() for k in range(nb))
         loss.backward()
@@ -386,11 +386,16 @@ def extras():
 
     forward_only()
     forward_backward()
+    forward_backward(True)
     _, t_fwd = _timed(forward_only)
-    _, t_all = _timed(forward_backward)
+    (gf64, gb64), t_all = _timed(forward_backward)
+    (gf32, gb32), t_mix = _timed(lambda: forward_backward(True))
     out["adjoint_16x_h256"] = {"instances": nb, "unknowns_each": dofs(N), "tol": 1e-10,
                                "forward_ms": 1e3 * t_fwd, "forward_and_gradients_ms": 1e3 * t_all,
-                               "ratio": t_all / t_fwd}
+                               "ratio": t_all / t_fwd,
+                               "fp32_refine_forward_and_gradients_ms": 1e3 * t_mix,
+                               "fp32_refine_rel_diff_df": float((gf32 - gf64).abs().max() / gf64.abs().max()),
+                               "fp32_refine_rel_diff_dbeta": float(((gb32 - gb64).abs() / gb64.abs()).max())}
     torch.cuda.empty_cache()
 
     # implicit Euler: four time steps dt marching together at h = 1/256, f = sin(pi x) sin(pi y)

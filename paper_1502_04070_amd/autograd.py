@@ -10,6 +10,8 @@ multigrid:
     dL/df = M_full[interior, :]^T lambda_u      (all lattice points)
     dL/dg = Pi^T M_P lambda_p
     dL/dbeta = -lambda_u^T M u                  (d calA / d beta = diag(M, M, 0)).
+With mixed=True both solves are FP32 cycles inside FP64 iterative refinement
+(the FP64 residual and projection decide convergence), else FP64 cycles.
 Every step runs in the HIP library (loads, masses, projections, solves, dots);
 this module only wires them into torch.autograd.
 """
@@ -40,16 +42,16 @@ class StokesSolve(torch.autograd.Function):
     """(f_nodal (2,M,M), g_nodal (N+1,N+1), beta (0-d)) -> (u, p)."""
 
     @staticmethod
-    def forward(ctx, f_nodal, g_nodal, beta, rtol, maxit, opts):
+    def forward(ctx, f_nodal, g_nodal, beta, rtol, maxit, mixed, opts):
         N = f_nodal.shape[-1] // 2
         h = hierarchy(N, _beta_value(beta), **opts)
         g = g_nodal.detach().clone().contiguous()
         h.project_mean(g)
         fu, gp = h.load(f_nodal.detach().contiguous(), g)
-        u, p, info = h.solve(fu, gp, rtol=rtol, maxit=maxit)
+        u, p, info = (h.solve_mixed if mixed else h.solve)(fu, gp, rtol=rtol, maxit=maxit)
         if info.status != "ok":
             raise RuntimeError(f"forward solve: {info}")
-        ctx.h, ctx.rtol, ctx.maxit = h, rtol, maxit
+        ctx.h, ctx.rtol, ctx.maxit, ctx.mixed = h, rtol, maxit, mixed
         ctx.beta_is_tensor = torch.is_tensor(beta)
         ctx.save_for_backward(u, p)
         return u, p
@@ -61,7 +63,7 @@ class StokesSolve(torch.autograd.Function):
         ru = torch.zeros_like(u) if gu is None else gu.contiguous().clone()
         rp = torch.zeros_like(p) if gp is None else gp.contiguous().clone()
         h.project_dual(rp)
-        lu, lp, info = h.solve(ru, rp, rtol=ctx.rtol, maxit=ctx.maxit)
+        lu, lp, info = (h.solve_mixed if ctx.mixed else h.solve)(ru, rp, rtol=ctx.rtol, maxit=ctx.maxit)
         if info.status != "ok":
             raise RuntimeError(f"adjoint solve: {info}")
         df = h.mass(lu, all_nodes=True)
@@ -70,12 +72,13 @@ class StokesSolve(torch.autograd.Function):
         dbeta = None
         if ctx.beta_is_tensor and ctx.needs_input_grad[2]:
             dbeta = -h.dot(lu, h.mass(u), 0).reshape(())
-        return df, dg, dbeta, None, None, None
+        return df, dg, dbeta, None, None, None, None
 
 
-def stokes_solve(f_nodal, g_nodal, beta, rtol: float = 1e-10, maxit: int = 500, **opts):
-    """Differentiable solve; gradients flow to f_nodal, g_nodal and beta (a tensor)."""
-    return StokesSolve.apply(f_nodal, g_nodal, beta, rtol, maxit, opts)
+def stokes_solve(f_nodal, g_nodal, beta, rtol: float = 1e-10, maxit: int = 500, mixed: bool = False, **opts):
+    """Differentiable solve; gradients flow to f_nodal, g_nodal and beta (a tensor).
+    mixed: FP32 cycles inside FP64 iterative refinement for both solves."""
+    return StokesSolve.apply(f_nodal, g_nodal, beta, rtol, maxit, bool(mixed), opts)
 
 
 class MassProduct(torch.autograd.Function):
@@ -117,7 +120,7 @@ class BatchStokesSolve(torch.autograd.Function):
     """Stacked instances of one size: f (B,2,M,M), g (B,N+1,N+1), beta (B,) -> (u, p) stacked."""
 
     @staticmethod
-    def forward(ctx, f, g, beta, rtol, maxit, opts):
+    def forward(ctx, f, g, beta, rtol, maxit, mixed, opts):
         nb, N = f.shape[0], f.shape[-1] // 2
         betas = beta.detach().cpu().tolist() if torch.is_tensor(beta) else [float(v) for v in beta]
         B = batch([N] * nb, betas, **opts)
@@ -128,12 +131,12 @@ class BatchStokesSolve(torch.autograd.Function):
             fu, gp = h.load(f[k].detach().contiguous(), gk)
             fus.append(fu)
             gps.append(gp)
-        us, ps, infos = B.solve(fus, gps, rtol=rtol, maxit=maxit)
+        us, ps, infos = (B.solve_mixed if mixed else B.solve)(fus, gps, rtol=rtol, maxit=maxit)
         if any(i.status != "ok" for i in infos):
             raise RuntimeError(f"batched forward solve: {infos}")
         u = torch.stack(us)
         p = torch.stack(ps)
-        ctx.B, ctx.rtol, ctx.maxit = B, rtol, maxit
+        ctx.B, ctx.rtol, ctx.maxit, ctx.mixed = B, rtol, maxit, mixed
         ctx.beta_is_tensor = torch.is_tensor(beta)
         ctx.save_for_backward(u, p)
         return u, p
@@ -149,7 +152,7 @@ class BatchStokesSolve(torch.autograd.Function):
             h.project_dual(rp)
             rus.append(ru)
             rps.append(rp)
-        lus, lps, infos = B.solve(rus, rps, rtol=ctx.rtol, maxit=ctx.maxit)
+        lus, lps, infos = (B.solve_mixed if ctx.mixed else B.solve)(rus, rps, rtol=ctx.rtol, maxit=ctx.maxit)
         if any(i.status != "ok" for i in infos):
             raise RuntimeError(f"batched adjoint solve: {infos}")
         dfs, dgs, dbs = [], [], []
@@ -161,9 +164,10 @@ class BatchStokesSolve(torch.autograd.Function):
             if ctx.beta_is_tensor:
                 dbs.append(-h.dot(lus[k], h.mass(u[k].contiguous()), 0).reshape(()))
         dbeta = torch.stack(dbs) if ctx.beta_is_tensor and ctx.needs_input_grad[2] else None
-        return torch.stack(dfs), torch.stack(dgs), dbeta, None, None, None
+        return torch.stack(dfs), torch.stack(dgs), dbeta, None, None, None, None
 
 
-def batch_stokes_solve(f, g, beta, rtol: float = 1e-10, maxit: int = 500, **opts):
-    """Differentiable batched solve of B instances of one size."""
-    return BatchStokesSolve.apply(f, g, beta, rtol, maxit, opts)
+def batch_stokes_solve(f, g, beta, rtol: float = 1e-10, maxit: int = 500, mixed: bool = False, **opts):
+    """Differentiable batched solve of B instances of one size.
+    mixed: FP32 cycles inside FP64 iterative refinement for both solves."""
+    return BatchStokesSolve.apply(f, g, beta, rtol, maxit, bool(mixed), opts)
