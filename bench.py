@@ -403,14 +403,22 @@ def extras():
     dts = [1e-1, 1e-2, 1e-3, 1e-4]
     Fs, _ = inputs.smooth_plus_noise(N, seed=0, noise=0.0)
     Fd = torch.from_numpy(Fs).cuda()
-    te = BatchImplicitEuler([N] * len(dts), dts)
-    te.step([Fd] * len(dts))
     nsteps = 10
-    infos, t_steps = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
-    out["implicit_euler_4dt_h256"] = {
-        "dts": dts, "steps": nsteps, "tol": 1e-10, "ms_per_step": 1e3 * t_steps / nsteps,
-        "iterations_last_step": [i.iters for i in infos[-1]]}
-    del te
+    rec, finals = {"dts": dts, "steps": nsteps, "tol": 1e-10}, {}
+    for mixed in (False, True):
+        te = BatchImplicitEuler([N] * len(dts), dts, mixed=mixed)
+        te.step([Fd] * len(dts))
+        infos, t_steps = _timed(lambda: [te.step([Fd] * len(dts)) for _ in range(nsteps)])
+        key = "fp32_refine_" if mixed else ""
+        rec[key + "ms_per_step"] = 1e3 * t_steps / nsteps
+        rec[key + "iterations_last_step"] = [i.iters for i in infos[-1]]
+        finals[mixed] = [u.clone() for u in te.us]
+        del te
+    # the same eleven steps in both precisions: largest velocity difference, relative to the FP64 state
+    rec["fp32_refine_rel_diff_u"] = max(float((a - b).abs().max() / b.abs().max())
+                                        for a, b in zip(finals[True], finals[False]))
+    out["implicit_euler_4dt_h256"] = rec
+    del finals
     torch.cuda.empty_cache()
 
     # damping per level, searched for each beta of the main workload (h = 1/128)

@@ -270,6 +270,10 @@ int smg_get_damping(smg_t h, int level, double* tau, double* sigma);
  */
 int smg_implicit_step(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
                       double* u, double* p, int* iters, double* relres, smg_stream_t s);
+/* smg_implicit_step solved as smg_solve_mixed: FP32 cycles inside FP64
+ * iterative refinement (same arguments and status codes). */
+int smg_implicit_step_mixed(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
+                            double* u, double* p, int* iters, double* relres, smg_stream_t s);
 
 /*
  * Single-precision cycle (exposed for testing the FP32 kernels): one iterate
@@ -337,6 +341,11 @@ int smg_batch_set_damping(smg_batch_t b, int instance, int level, double tau, do
 int smg_batch_implicit_step(smg_batch_t b, const double* const* f_nodal, const double* const* g_nodal,
                             double rtol, int maxit, double* const* u, double* const* p, int* iters,
                             double* relres, int* status, smg_stream_t s);
+/* smg_batch_implicit_step solved as smg_batch_solve_mixed (FP32 cycles inside
+ * FP64 iterative refinement). */
+int smg_batch_implicit_step_mixed(smg_batch_t b, const double* const* f_nodal, const double* const* g_nodal,
+                                  double rtol, int maxit, double* const* u, double* const* p, int* iters,
+                                  double* relres, int* status, smg_stream_t s);
 
 /*
  * Batched kernel timing (profiling support): `reps` back-to-back launches of

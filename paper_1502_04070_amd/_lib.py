@@ -68,7 +68,9 @@ SIGNATURES = {
     "smg_get_damping": [P, I, C.POINTER(D), C.POINTER(D)],
     "smg_batch_set_damping": [P, I, I, D, D],
     "smg_implicit_step": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), P],
+    "smg_implicit_step_mixed": [P, P, P, D, I, P, P, C.POINTER(I), C.POINTER(D), P],
     "smg_batch_implicit_step": [P, P, P, D, I, P, P, P, P, P, P],
+    "smg_batch_implicit_step_mixed": [P, P, P, D, I, P, P, P, P, P, P],
     "smg_tune": [I, C.POINTER(I), C.POINTER(D), C.POINTER(SmgParams), I, C.POINTER(SmgParams),
                  C.POINTER(D), C.POINTER(SmgParams), C.POINTER(D), I, C.POINTER(I), P],
     "smg_batch_solve": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),

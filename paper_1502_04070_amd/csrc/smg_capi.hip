@@ -1224,15 +1224,27 @@ static void implicit_rhs(smg_hier* H, const double* f_nodal, const double* g_nod
   else launch_fill(T.t.p, T.n_p, 0.0, s);
 }
 
-int smg_implicit_step(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
-                      double* u, double* p, int* iters, double* relres, smg_stream_t sv) {
+// The right-hand side is built in the finest level's scratch vector t; both
+// solves copy it into f before the mixed one reuses t for its FP64 residual.
+static int implicit_step(smg_t h, bool mixed, const double* f_nodal, const double* g_nodal, double rtol,
+                         int maxit, double* u, double* p, int* iters, double* relres, smg_stream_t sv) {
   if (!h) return fail(SMG_EINVAL, "null handle");
   if (!u || !p) return fail(SMG_EINVAL, "null vector");
   HIPCHK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)sv;
   implicit_rhs(h, f_nodal, g_nodal, u, s);
   Level& T = h->lv[h->L];
-  return run_solve(h, false, T.t.u, T.t.p, rtol, maxit, u, p, iters, relres, nullptr, s);
+  return run_solve(h, mixed, T.t.u, T.t.p, rtol, maxit, u, p, iters, relres, nullptr, s);
+}
+
+int smg_implicit_step(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
+                      double* u, double* p, int* iters, double* relres, smg_stream_t sv) {
+  return implicit_step(h, false, f_nodal, g_nodal, rtol, maxit, u, p, iters, relres, sv);
+}
+
+int smg_implicit_step_mixed(smg_t h, const double* f_nodal, const double* g_nodal, double rtol, int maxit,
+                            double* u, double* p, int* iters, double* relres, smg_stream_t sv) {
+  return implicit_step(h, true, f_nodal, g_nodal, rtol, maxit, u, p, iters, relres, sv);
 }
 
 int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, int maxit,

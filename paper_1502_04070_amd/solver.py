@@ -294,10 +294,11 @@ class Hierarchy:
         _lib.check(self.lib.smg_get_damping(self.h, int(level), C.byref(t), C.byref(sg)), "smg_get_damping")
         return t.value, sg.value
 
-    def implicit_step(self, u, p, f_nodal=None, g_nodal=None, rtol=1e-10, maxit=200):
+    def implicit_step(self, u, p, f_nodal=None, g_nodal=None, rtol=1e-10, maxit=200, mixed=False):
         """One implicit Euler step with dt = 1 / beta of this hierarchy, in place:
         (u, p) = (u^n, guess) -> (u^{n+1}, p^{n+1}).  f_nodal: nodal values at all
-        P2 lattice points, g_nodal: P1 nodal values with zero integral."""
+        P2 lattice points, g_nodal: P1 nodal values with zero integral.  mixed:
+        FP32 cycles inside FP64 iterative refinement."""
         L = self.L
         self._chk(L, (u, "u"), (p, "p"))
         if f_nodal is not None:
@@ -305,9 +306,10 @@ class Hierarchy:
         if g_nodal is not None:
             self._chk(L, (g_nodal, "p"))
         it, rel = C.c_int(), C.c_double()
-        code = self.lib.smg_implicit_step(self.h, _ptr(f_nodal), _ptr(g_nodal), float(rtol), int(maxit),
-                                          _ptr(u), _ptr(p), C.byref(it), C.byref(rel), _stream())
-        _lib.check(code, "smg_implicit_step", soft_ok=True)
+        name = "smg_implicit_step_mixed" if mixed else "smg_implicit_step"
+        code = getattr(self.lib, name)(self.h, _ptr(f_nodal), _ptr(g_nodal), float(rtol), int(maxit),
+                                       _ptr(u), _ptr(p), C.byref(it), C.byref(rel), _stream())
+        _lib.check(code, name, soft_ok=True)
         return SolveInfo(_lib.STATUS[code], it.value, rel.value, [])
 
     def error_norm(self, u, p, us, ps) -> float:
@@ -421,7 +423,7 @@ class Batch:
         _lib.check(self.lib.smg_batch_set_damping(self.b, int(instance), int(level), float(tau), float(sigma)),
                    "smg_batch_set_damping")
 
-    def implicit_step(self, us, ps, f_nodals=None, g_nodals=None, rtol=1e-10, maxit=200):
+    def implicit_step(self, us, ps, f_nodals=None, g_nodals=None, rtol=1e-10, maxit=200, mixed=False):
         """Hierarchy.implicit_step for every instance (dt_k = 1 / beta_k), in place."""
         n = self.n
         for k, h in enumerate(self.instances):
@@ -434,10 +436,11 @@ class Batch:
         it = (C.c_int * n)()
         rel = (C.c_double * n)()
         st = (C.c_int * n)()
-        code = self.lib.smg_batch_implicit_step(self.b, arr(f_nodals) if f_nodals is not None else None,
-                                                arr(g_nodals) if g_nodals is not None else None, float(rtol),
-                                                int(maxit), arr(us), arr(ps), it, rel, st, _stream())
-        _lib.check(code, "smg_batch_implicit_step", soft_ok=True)
+        name = "smg_batch_implicit_step_mixed" if mixed else "smg_batch_implicit_step"
+        code = getattr(self.lib, name)(self.b, arr(f_nodals) if f_nodals is not None else None,
+                                       arr(g_nodals) if g_nodals is not None else None, float(rtol),
+                                       int(maxit), arr(us), arr(ps), it, rel, st, _stream())
+        _lib.check(code, name, soft_ok=True)
         return [SolveInfo(_lib.STATUS[st[k]], it[k], rel[k], []) for k in range(n)]
 
     def solve_mixed(self, fus, gps, rtol=1e-10, maxit=400, us=None, ps=None):

@@ -6,7 +6,8 @@ system calA(beta) with right-hand side (M_full f + beta M u^n, M_P g).  The
 library forms that right-hand side and solves the step warm-started from the
 previous state (smg_implicit_step); a hierarchy is set up once per dt and
 reused for every step.  Several dt (or several trajectories) march together
-as one batch.
+as one batch.  mixed=True solves each step with FP32 cycles inside FP64
+iterative refinement (smg_implicit_step_mixed).
 """
 from __future__ import annotations
 
@@ -16,10 +17,11 @@ from .solver import Batch, Hierarchy
 class ImplicitEuler:
     """One trajectory: state (u, p) on an h = 1/N grid, time step dt."""
 
-    def __init__(self, N: int, dt: float, u0=None, **kw):
+    def __init__(self, N: int, dt: float, u0=None, mixed: bool = False, **kw):
         if not dt > 0:
             raise ValueError("dt must be positive")
         self.dt = float(dt)
+        self.mixed = bool(mixed)
         self.h = Hierarchy(N, 1.0 / self.dt, **kw)
         self.u, self.p = self.h.zeros()
         if u0 is not None:
@@ -27,7 +29,7 @@ class ImplicitEuler:
         self.t = 0.0
 
     def step(self, f_nodal=None, g_nodal=None, rtol=1e-10, maxit=200):
-        info = self.h.implicit_step(self.u, self.p, f_nodal, g_nodal, rtol=rtol, maxit=maxit)
+        info = self.h.implicit_step(self.u, self.p, f_nodal, g_nodal, rtol=rtol, maxit=maxit, mixed=self.mixed)
         if info.status != "ok":
             raise RuntimeError(f"implicit step at t={self.t}: {info}")
         self.t += self.dt
@@ -45,10 +47,11 @@ class ImplicitEuler:
 class BatchImplicitEuler:
     """Several trajectories (sizes Ns, time steps dts) stepped together."""
 
-    def __init__(self, Ns, dts, u0s=None, **kw):
+    def __init__(self, Ns, dts, u0s=None, mixed: bool = False, **kw):
         if any(not dt > 0 for dt in dts):
             raise ValueError("dt must be positive")
         self.dts = [float(dt) for dt in dts]
+        self.mixed = bool(mixed)
         self.B = Batch(list(Ns), [1.0 / dt for dt in self.dts], **kw)
         outs = [h.zeros() for h in self.B.instances]
         self.us = [u for u, _ in outs]
@@ -59,7 +62,8 @@ class BatchImplicitEuler:
         self.steps = 0
 
     def step(self, f_nodals=None, g_nodals=None, rtol=1e-10, maxit=200):
-        infos = self.B.implicit_step(self.us, self.ps, f_nodals, g_nodals, rtol=rtol, maxit=maxit)
+        infos = self.B.implicit_step(self.us, self.ps, f_nodals, g_nodals, rtol=rtol, maxit=maxit,
+                                     mixed=self.mixed)
         bad = [i for i in infos if i.status != "ok"]
         if bad:
             raise RuntimeError(f"batched implicit step {self.steps}: {bad[:3]}")

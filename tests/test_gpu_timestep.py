@@ -14,10 +14,11 @@ from tests.test_gpu_ops import dev, host, oracle_level
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "fp32_refine"])
 @pytest.mark.parametrize("dt", [1e-3, 0.1])
-def test_steps_match_oracle(dt):
+def test_steps_match_oracle(dt, mixed):
     N = 32
-    print(f"implicit steps N={N} dt={dt}", flush=True)
+    print(f"implicit steps N={N} dt={dt} mixed={mixed}", flush=True)
     oh = oracle_level(N, 1.0 / dt, 2)
     lv, d = oh.top, oh.discs[-1]
     F, _ = inputs.normal_fg(N, seed=80, with_g=False)
@@ -25,10 +26,10 @@ def test_steps_match_oracle(dt):
     G = np.zeros((N + 1, N + 1))
     fn, _ = lat.lattice_to_nodal(d, F, G)
     xs = ots.march(lv, lat.from_lattice(d, u0, G)[: lv.nu2], 4, fn)
-    ts = ImplicitEuler(N, dt, u0=dev(u0))
+    ts = ImplicitEuler(N, dt, u0=dev(u0), mixed=mixed)
     Fd = dev(F)
     for k in range(4):
-        info = ts.step(Fd, rtol=1e-13, maxit=300)
+        info = ts.step(Fd, rtol=1e-12 if mixed else 1e-13, maxit=300)
         got = lat.from_lattice(d, host(ts.u), host(ts.p))
         err = np.linalg.norm(got - xs[k]) / np.linalg.norm(xs[k])
         assert err <= 1e-9, (k, err, info)
@@ -55,13 +56,14 @@ def test_step_with_divergence_data_and_warm_start():
     assert i2.iters < i1.iters
 
 
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "fp32_refine"])
 @pytest.mark.parametrize("domain", ["square", "l_shape", "union_jack"])
-def test_batched_steps_match_single(domain):
+def test_batched_steps_match_single(domain, mixed):
     Ns, dts = [32, 64, 32], [1e-2, 1e-3, 1.0]
     u0s = [dev(inputs.random_state(N, seed=90 + k)[0]) for k, N in enumerate(Ns)]
     Fs = [dev(inputs.normal_fg(N, seed=95 + k, with_g=False)[0]) for k, N in enumerate(Ns)]
-    bt = BatchImplicitEuler(Ns, dts, u0s=u0s, domain=domain)
-    singles = [ImplicitEuler(N, dt, u0=u0, domain=domain) for N, dt, u0 in zip(Ns, dts, u0s)]
+    bt = BatchImplicitEuler(Ns, dts, u0s=u0s, domain=domain, mixed=mixed)
+    singles = [ImplicitEuler(N, dt, u0=u0, domain=domain, mixed=mixed) for N, dt, u0 in zip(Ns, dts, u0s)]
     for _ in range(3):
         binfo = bt.step(Fs, rtol=1e-12, maxit=300)
         for k, ts in enumerate(singles):
