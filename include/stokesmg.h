@@ -125,6 +125,7 @@ const char* smg_last_error(void);
  * Synchronous.  Errors: SMG_EINVAL, SMG_ENOMEM, SMG_ESINGULAR, SMG_EHIP.
  */
 int smg_setup(int N, double beta, const smg_params* prm, smg_t* out);
+/* Frees the hierarchy and everything it owns; NULL is accepted (no-op). */
 int smg_destroy(smg_t h);
 
 /* Levels are numbered 0 (coarsest, n0 cells) .. L (finest, N cells). */
@@ -309,6 +310,7 @@ typedef struct smg_batch_s* smg_batch_t;
 
 int smg_batch_setup(int n, const int* N, const double* beta, const smg_params* prm,
                     smg_batch_t* out);
+/* Frees the batch and its hierarchies; NULL is accepted (no-op). */
 int smg_batch_destroy(smg_batch_t b);
 int smg_batch_size(smg_batch_t b);
 /* The hierarchy of instance k (for smg_load, smg_apply, ... on its levels);

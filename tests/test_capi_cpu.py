@@ -76,3 +76,21 @@ def test_setup_rejects_bad_arguments(lib, N, beta, mod, needle):
 def test_null_handle_is_rejected(lib):
     assert lib.smg_apply(None, 0, None, None, None, None, None) == -1
     assert lib.smg_solve(None, None, None, 1e-8, 10, None, None, None, None, None, None) == -1
+
+
+def test_every_entry_point_rejects_a_null_handle(lib):
+    """Each entry point that takes a hierarchy or a batch returns SMG_EINVAL
+    with a message for a null handle (and null vectors), before touching the
+    device; destroying NULL is a no-op."""
+    import ctypes as C
+    skip = {"smg_setup", "smg_batch_setup", "smg_default_params", "smg_tune"}
+    for name, args in _lib.SIGNATURES.items():
+        if name in skip:
+            continue
+        vals = [1 if a is C.c_int else 1e-8 if a is C.c_double else None for a in args]
+        rc = getattr(lib, name)(*vals)
+        if name in ("smg_destroy", "smg_batch_destroy"):
+            assert rc == 0, name
+        else:
+            assert rc == -1, (name, rc)
+            assert lib.smg_last_error().decode(), name
