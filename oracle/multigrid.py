@@ -131,7 +131,7 @@ def ne_step(lv: Level, x: np.ndarray, f: np.ndarray, tau: float) -> np.ndarray:
     """Normal-equation smoother: x + tau L^{-1} A L^{-1} (f - A x)."""
     r = f - lv.calA @ x
     y = r / lv.Ldiag
-    return x + tau * (lv.calA @ y) / lv.Ldiag
+    return x + x.dtype.type(tau) * (lv.calA @ y) / lv.Ldiag
 
 
 def uzawa_step(lv: Level, x: np.ndarray, f: np.ndarray, tau: float, sigma: float) -> np.ndarray:
@@ -143,6 +143,7 @@ def uzawa_step(lv: Level, x: np.ndarray, f: np.ndarray, tau: float, sigma: float
     nu2 = lv.nu2
     u, p = x[:nu2], x[nu2:]
     fu, g = f[:nu2], f[nu2:]
+    tau, sigma = x.dtype.type(tau), x.dtype.type(sigma)
     Au = lv.A @ u
     u_half = u + tau * (fu - Au - lv.Bt @ p) / lv.Ahat
     p_new = p - sigma * (g - lv.B @ u_half) / lv.Shat
@@ -180,7 +181,9 @@ def cycle(h: Hierarchy, k: int, x: np.ndarray, f: np.ndarray, prm: Params) -> np
     for _ in range(prm.nu_pre):
         x = smooth(lv, x, f, prm, k)
     rc = restrict_residual(h, k, x, f)
-    z = np.zeros(h.levels[k - 1].n)
+    # the coarse correction starts from zero in the arithmetic of the cycle
+    # (float32 when the cycle runs in single precision)
+    z = np.zeros(h.levels[k - 1].n, dtype=rc.dtype)
     for _ in range(prm.gamma):
         z = cycle(h, k - 1, z, rc, prm)
     x = x + lv.P @ z

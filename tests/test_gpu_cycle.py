@@ -150,25 +150,44 @@ def test_initial_guess_boundary_ignored_and_restart():
     assert float(U2[:, 0, :].abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("kind", ["ne", "uzawa", "ne_w"])
 @pytest.mark.parametrize("beta", [1.0, 1e4])
-def test_fp32_cycle_matches_oracle_fp32_cycle(beta):
+def test_fp32_cycle_matches_oracle_fp32_cycle(beta, kind):
+    """One FP32 cycle from an FP32 iterate against the oracle's FP32 cycle
+    (single precision at every level, coarsest level solved in FP64): the two
+    agree to FP32 rounding (1e-6 of the update; the FP32 cycle itself differs
+    from the FP64 one by about 1e-7 of it), and the GPU result is farther than
+    FP64 rounding from the FP64 cycle, so the GPU cycle does run in FP32."""
+    print(f"fp32 cycle {kind} beta={beta}", flush=True)
     N = 64
+    gkw, prm = _params(kind)
     oh = oracle_level(N, beta, 2)
-    gh = gpu_hier(N, beta)
+    gh = gpu_hier(N, beta, **gkw)
     F, G = inputs.normal_fg(N, seed=40)
     f, FU, GP = _rhs(gh, oh, F, G)
     d = oh.discs[-1]
     x0 = oh.top.project_mean(np.random.default_rng(3).standard_normal(oh.top.n))
-    u0, p0 = lat.to_lattice(d, x0)
+    x0_32, f_32 = x0.astype(np.float32), f.astype(np.float32)
+    u0, p0 = lat.to_lattice(d, x0_32.astype(np.float64))
     U = dev(u0).float()
     P = dev(p0).float()
     gh.cycle_f32(FU.float(), GP.float(), U, P)
     h32 = omixed._Hierarchy32(oh)
-    x32 = mg.cycle(h32, oh.L, x0.astype(np.float32), f.astype(np.float32), mg.Params()).astype(np.float64)
+    x32 = mg.cycle(h32, oh.L, x0_32, f_32, prm)
+    assert x32.dtype == np.float32
+    x64 = mg.cycle(oh, oh.L, x0_32.astype(np.float64), f_32.astype(np.float64), prm)
     got = lat.from_lattice(d, host(U).astype(np.float64), host(P).astype(np.float64))
     lv = oh.top
-    diff = lv.project_mean(got) - lv.project_mean(x32)
-    assert np.linalg.norm(diff) <= 1e-5 * np.linalg.norm(lv.project_mean(x32) - x0)
+    ref32 = lv.project_mean(x32.astype(np.float64))
+    ref64 = lv.project_mean(x64)
+    upd = np.linalg.norm(ref64 - lv.project_mean(x0_32.astype(np.float64)))
+    gotp = lv.project_mean(got)
+    e32 = np.linalg.norm(gotp - ref32) / upd
+    e64 = np.linalg.norm(gotp - ref64) / upd
+    o3264 = np.linalg.norm(ref32 - ref64) / upd
+    print(f"  |gpu-oracle32|={e32:.2e} |gpu-oracle64|={e64:.2e} |oracle32-oracle64|={o3264:.2e}", flush=True)
+    assert e32 <= 1e-6, e32
+    assert e64 >= 1e-9, e64
 
 
 @pytest.mark.parametrize("beta", [1.0, 1e4])
