@@ -43,12 +43,39 @@ def dofs(N):
     return 2 * (2 * N - 1) ** 2 + (N + 1) ** 2
 
 
+# Algorithmic bytes of one normal-equation smoothing step, per FP64 unknown:
+# the step as stated (residual, scaled residual, operator, update) streams six
+# vectors of the unknowns once each -- read x and F, write y = L^-1 (F - A x),
+# read y and x, write x -- so 6 words = 48 B per unknown.  This is the figure
+# the roofline fraction is quoted against.
+MODEL_NE_STEP_BYTES_PER_DOF = 48
+
+
+def ne_step_model_bytes(N):
+    return MODEL_NE_STEP_BYTES_PER_DOF * dofs(N)
+
+
 def ne_step_bytes(N):
-    """Algorithmic HBM bytes of one fused normal-equation step on one instance
-    (x <- x + tau L^-1 A L^-1 (F - A x)): read x and F (all unknowns), read
-    Shat^-1 (one per pressure node), write the new x; 8-byte words, each once."""
+    """The fused kernel's own minimum HBM bytes for one normal-equation step on
+    one instance: read x and F (all unknowns), read Shat^-1 (one per pressure
+    node), write the new x; 8-byte words, each once (the intermediate y stays
+    on chip)."""
     n, npres = dofs(N), (N + 1) ** 2
     return 8 * (3 * n + npres)
+
+
+def roofline_block(kernel, Ns, avg_ms, traffic=None):
+    """The roofline object of one timed launch over instances of sizes Ns."""
+    model = sum(ne_step_model_bytes(N) for N in Ns)
+    own = sum(ne_step_bytes(N) for N in Ns)
+    achieved = model / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": model, "bytes_per_dof": MODEL_NE_STEP_BYTES_PER_DOF,
+            "unknowns_per_launch": sum(dofs(N) for N in Ns), "avg_launch_us": avg_ms * 1e3,
+            "kernel_min_bytes_per_launch": own,
+            "kernel_min_GBps": own / (avg_ms * 1e-3) / 1e9,
+            "kernel_min_frac": own / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def ne_kernel_source_hash():
@@ -242,12 +269,18 @@ def _timed(fn):
     return out, time.perf_counter() - t0
 
 
-def extras():
-    """The other workloads, each timed once after a warm-up run on resident inputs."""
+EXTRA_SECTIONS = ("batch64x4", "shares8", "mixed512", "adjoint", "implicit", "damping", "lshape",
+                  "smoothers", "protocol")
+
+
+def extras(sections=EXTRA_SECTIONS):
+    """The other workloads, each timed once after a warm-up run on resident
+    inputs; `sections` selects some of them (names in EXTRA_SECTIONS)."""
     import numpy as np
     import torch
     from paper_1502_04070_amd import Batch, Hierarchy, inputs
     from paper_1502_04070_amd import autograd as ag
+    from paper_1502_04070_amd import tune
 
     out = {}
     # 64 instances x 4 right-hand sides, h = 1/32 ... 1/256, one batch
@@ -258,8 +291,24 @@ def extras():
             Ns.append(N)
             betas.append(beta)
             fg.append((F, G))
-    from paper_1502_04070_amd import tune
-    sched, _ = tune.schedule_for(Ns, betas, iters=5)
+    if "batch64x4" in sections or "shares8" in sections:
+        sched, _ = tune.schedule_for(Ns, betas, iters=5)
+    if "batch64x4" in sections:
+        out.update(_batch64x4(Ns, betas, fg, sched))
+    if "shares8" in sections:
+        out.update(_shares8(Ns, betas, fg, sched, out))
+    for name in ("mixed512", "adjoint", "implicit", "damping", "lshape", "smoothers", "protocol"):
+        if name in sections:
+            out.update(globals()["_x_" + name]())
+            torch.cuda.empty_cache()
+    return out
+
+
+def _batch64x4(Ns, betas, fg, sched):
+    import numpy as np
+    import torch
+    from paper_1502_04070_amd import Batch
+    out = {}
     B = Batch(Ns, betas, schedule=sched)
     fus, gps = [], []
     for h, (F, G) in zip(B.instances, fg):
@@ -287,12 +336,23 @@ def extras():
              "dof_cycles_per_s": float((dof * its).sum() / dt)}
         if name == "fp64":
             gbs = MODEL_BYTES_PER_DOF_V22 * float((dof * its).sum()) / dt / 1e9
-            r["model_hbm_GBps"] = gbs
-            r["model_hbm_frac"] = gbs / HBM_PEAK_GBS
+            r["per_cycle_model_GBps"] = gbs
+            r["per_cycle_model_frac"] = gbs / HBM_PEAK_GBS
         rec[name] = r
+    # the dominant kernel of this workload: the batched finest-level
+    # normal-equation step of all 256 instances, timed with HIP events
+    rec["roofline"] = roofline_block("finest-level fused normal-equation step, all 256 instances (k_ne_b)",
+                                     Ns, B.time_kernel(0, reps=50))
     out["batch_64x4_h32_to_h256"] = rec
     del B, fus, gps, us, ps
     torch.cuda.empty_cache()
+    return out
+
+
+def _shares8(Ns, betas, fg, sched, prev):
+    import torch
+    from paper_1502_04070_amd import Batch
+    out = {}
 
     # The same 256 solves as the shares of an 8-GPU run: independent instances
     # need no communication, so each GPU gets a batch of its own, placed
@@ -334,9 +394,15 @@ def extras():
         "rule": "longest first by unknowns", "solves_per_share": [len(sh) for sh in shares],
         "unknowns_per_share": [int(v) for v in load], "iterates_per_share": share_its,
         "fp64_time_to_tol_ms_per_share": share_ms, "slowest_share_ms": max(share_ms),
-        "one_gpu_whole_batch_ms": rec["fp64"]["time_to_tol_ms"]}
+        "one_gpu_whole_batch_ms": prev.get("batch_64x4_h32_to_h256", {}).get("fp64", {}).get("time_to_tol_ms")}
+    return out
 
-    # h = 1/512, FP64 against FP32 cycles in FP64 refinement, to 1e-10
+
+def _x_mixed512():
+    """h = 1/512, FP64 against FP32 cycles in FP64 refinement, to 1e-10."""
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs, tune
+    out = {}
     N = 512
     F, G = inputs.smooth_plus_noise(N, seed=0)
     sched, _ = tune.schedule_for([N], [1.0], iters=10)
@@ -358,11 +424,25 @@ def extras():
         den = torch.sqrt((u64 ** 2).sum() + (p64 ** 2).sum())
         r["rel_diff_fp32_refine_vs_fp64"] = float(num / den)
         rec[f"beta={beta:g}"] = r
+        if beta == 1.0:
+            # the dominant kernel of the FP64 solve: the finest-level fused
+            # normal-equation step, timed with HIP events
+            from paper_1502_04070_amd import Batch
+            B1 = Batch([N], [beta], schedule=sched)
+            rec["roofline"] = roofline_block("finest-level fused normal-equation step, h=1/512 (k_ne_b)",
+                                             [N], B1.time_kernel(0, reps=100))
+            del B1
         del h
     out["mixed_h512"] = rec
-    torch.cuda.empty_cache()
+    return out
 
-    # 16 instances at h = 1/256: forward solve against forward + adjoint gradients
+
+def _x_adjoint():
+    """16 instances at h = 1/256: forward solve against forward + adjoint gradients."""
+    import torch
+    from paper_1502_04070_amd import inputs
+    from paper_1502_04070_amd import autograd as ag
+    out = {}
     N = 256
     ai = inputs.adjoint_instances()
     nb = len(ai)
@@ -396,10 +476,16 @@ def extras():
                                "fp32_refine_forward_and_gradients_ms": 1e3 * t_mix,
                                "fp32_refine_rel_diff_df": float((gf32 - gf64).abs().max() / gf64.abs().max()),
                                "fp32_refine_rel_diff_dbeta": float(((gb32 - gb64).abs() / gb64.abs()).max())}
-    torch.cuda.empty_cache()
+    return out
 
-    # implicit Euler: four time steps dt marching together at h = 1/256, f = sin(pi x) sin(pi y)
+
+def _x_implicit():
+    """Implicit Euler: four time steps dt marching together at h = 1/256, f = sin(pi x) sin(pi y)."""
+    import torch
+    from paper_1502_04070_amd import inputs
     from paper_1502_04070_amd.timestep import BatchImplicitEuler
+    out = {}
+    N = 256
     dts = [1e-1, 1e-2, 1e-3, 1e-4]
     Fs, _ = inputs.smooth_plus_noise(N, seed=0, noise=0.0)
     Fd = torch.from_numpy(Fs).cuda()
@@ -418,11 +504,15 @@ def extras():
     rec["fp32_refine_rel_diff_u"] = max(float((a - b).abs().max() / b.abs().max())
                                         for a, b in zip(finals[True], finals[False]))
     out["implicit_euler_4dt_h256"] = rec
-    del finals
-    torch.cuda.empty_cache()
+    return out
 
-    # damping per level, searched for each beta of the main workload (h = 1/128)
+
+def _x_damping():
+    """Damping per level, searched for each beta of the main workload (h = 1/128)."""
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs
     from paper_1502_04070_amd import tune as _tune
+    out = {}
     rec = {}
     F128, G128 = inputs.uniform_f(N_GRID, seed=0)
     for beta in BETAS:
@@ -437,9 +527,15 @@ def extras():
             r[name] = {"iterations": inf.iters, "time_to_tol_ms": 1e3 * dt_s}
         rec[str(beta)] = r
     out["level_damping_h128"] = rec
+    return out
 
-    # the L-shaped domain at h = 1/256 (three quarters of the square's
-    # unknowns), f iid U[-1, 1], g = 0, NE V(2,2) to 1e-8, next to the unit square
+
+def _x_lshape():
+    """The L-shaped domain at h = 1/256 (three quarters of the square's
+    unknowns), f iid U[-1, 1], g = 0, NE V(2,2) to 1e-8, next to the unit square."""
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs
+    out = {}
     N = 256
     F, G = inputs.uniform_f(N, seed=0)
     rec = {"tol": TOL}
@@ -455,8 +551,14 @@ def extras():
             del hh
         rec[f"beta={beta:g}"] = r
     out["l_shape_h256"] = rec
+    return out
 
-    # h = 1/128, the five betas: iterates to 1e-8 of NE and Uzawa V(3,3) and W(3,3)
+
+def _x_smoothers():
+    """h = 1/128, the five betas: iterates to 1e-8 of NE and Uzawa V(3,3) and W(3,3)."""
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs
+    out = {}
     F128, G128 = inputs.uniform_f(N_GRID, seed=0)
     rec = {"tol": TOL}
     for name, kw in (("ne_V33", dict(smoother="ne", nu_pre=3, nu_post=3)),
@@ -474,8 +576,14 @@ def extras():
             del hh
         rec[name] = r
     out["h128_smoothers_cycles"] = rec
-    torch.cuda.empty_cache()
+    return out
 
+
+def _x_protocol():
+    """The measurement protocol of Section 6 on the union-jack grid."""
+    import torch
+    from paper_1502_04070_amd import Hierarchy, inputs
+    out = {}
     # the measurement protocol of Section 6 on the union-jack grid (Tables 2
     # and 3): NE and Uzawa W(3,3), levels k = 4..8 (h = 1/32 .. 1/512), six
     # beta, x* = nodal values of the Section 6 fields (the paper projects
@@ -511,11 +619,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / h=1/512 / adjoint workloads")
-    ap.add_argument("--extras-only", action="store_true", help="only the batched / h=1/512 / adjoint workloads")
+    ap.add_argument("--extras-only", nargs="?", const=",".join(EXTRA_SECTIONS), default=None,
+                    metavar="SECTIONS",
+                    help="only the other workloads (comma list of: " + ", ".join(EXTRA_SECTIONS) + ")")
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only time the batched fused normal-equation step at h=1/N (no graphs)")
     ap.add_argument("--probe-count", type=int, default=1,
                     help="instances of the probe batch (5: the betas of the main workload)")
+    ap.add_argument("--probe-batch64x4", action="store_true",
+                    help="only time the finest-level normal-equation step of the 64 x 4 batch (no graphs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--cpu-extras", action="store_true",
@@ -538,19 +650,26 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.probe:
-        N, cnt = args.probe, args.probe_count
-        betas = BETAS if cnt == len(BETAS) else [1.0] * cnt
-        B = Batch([N] * cnt, betas)
+    if args.probe or args.probe_batch64x4:
+        if args.probe_batch64x4:
+            Ns = [N for N, _, rhs in inputs.batched_instances() for _ in rhs]
+            betas = [b for _, b, rhs in inputs.batched_instances() for _ in rhs]
+            name = "64 x 4 batch"
+        else:
+            Ns = [args.probe] * args.probe_count
+            betas = BETAS if args.probe_count == len(BETAS) else [1.0] * args.probe_count
+            name = f"h=1/{args.probe} x {args.probe_count}"
+        B = Batch(Ns, betas)
         ms = B.time_kernel(0, reps=args.kernel_reps)
-        nbytes = ne_step_bytes(N) * cnt
-        print(json.dumps({"probe": {"N": N, "instances": cnt, "kernel": "fused normal-equation step (default tile)",
-                                    "avg_launch_us": 1e3 * ms, "bytes_per_launch": nbytes,
-                                    "achieved_GBps": nbytes / (ms * 1e-3) / 1e9,
-                                    "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}), flush=True)
+        print(json.dumps({"probe": dict(roofline_block("fused normal-equation step (default tile), " + name,
+                                                       Ns, ms), reps=args.kernel_reps)}), flush=True)
         return
-    if args.extras_only:
-        print(json.dumps({"extras": extras()}), flush=True)
+    if args.extras_only is not None:
+        secs = [x for x in args.extras_only.split(",") if x]
+        bad = [x for x in secs if x not in EXTRA_SECTIONS]
+        if bad:
+            ap.error(f"unknown sections {bad}")
+        print(json.dumps({"extras": extras(secs)}), flush=True)
         return
     F, G = inputs.uniform_f(N_GRID, seed=0)
     Fd = torch.from_numpy(F).cuda()
@@ -621,8 +740,12 @@ def main():
     # dominant kernel: the batched finest-level fused normal-equation step,
     # timed with HIP events on the stream it runs on
     kern_ms = batch.time_kernel(0, reps=args.kernel_reps)
-    kbytes = ne_step_bytes(N_GRID) * len(BETAS)
-    achieved = kbytes / (kern_ms * 1e-3) / 1e9
+    roof = roofline_block("finest-level fused normal-equation step, all 5 instances (k_ne_b<double,16,8>)",
+                          [N_GRID] * len(BETAS), kern_ms, counter_traffic())
+    # the whole iterate against the model bytes of the cycle (304 B per
+    # unknown for an FP64 V(2,2) iterate)
+    roof["per_cycle_model_GBps"] = MODEL_BYTES_PER_DOF_V22 * dofs(N_GRID) * cycles / elapsed / 1e9
+    roof["per_cycle_model_frac"] = roof["per_cycle_model_GBps"] / HBM_PEAK_GBS
 
     out = {
         "metric": "velocity+pressure DOF*cycles/s (FP64 NE V(2,2) to 1e-8, h=1/128, 5 betas)",
@@ -654,17 +777,7 @@ def main():
             "time_to_tol_ms_batch": 1e3 * mixed_elapsed,
             "time_to_tol_ms_single": tt32,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "finest-level fused normal-equation step, all 5 instances (k_ne_b<double,16,8>)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic(),
-            "bytes_per_launch": kbytes,
-            "avg_launch_us": kern_ms * 1e3,
-        },
+        "roofline": roof,
     }
     if not args.no_extras:
         del batch, loads, fus, gps, outs, us, ps

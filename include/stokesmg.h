@@ -35,10 +35,15 @@
  * unless an entry point says so.
  *
  * STREAMS AND THREADS.  Every entry point enqueues on the given stream and
- * returns without waiting, except smg_setup, smg_destroy, smg_solve and
- * smg_solve_mixed, which synchronize the stream.  A handle owns scratch
- * buffers: calls on one handle must not overlap in time (use one stream per
- * handle, or one handle per concurrent stream).
+ * returns without waiting, except these, which wait for their work (and the
+ * stream) before they return: smg_setup, smg_destroy, smg_solve,
+ * smg_solve_mixed, smg_solve_error, smg_error_norm, smg_implicit_step,
+ * smg_implicit_step_mixed, smg_batch_setup, smg_batch_destroy,
+ * smg_batch_solve, smg_batch_solve_mixed, smg_batch_implicit_step,
+ * smg_batch_implicit_step_mixed, smg_time_kernel, smg_batch_time_kernel and
+ * smg_tune.  A handle owns scratch buffers: calls on one handle must not
+ * overlap in time (use one stream per handle, or one handle per concurrent
+ * stream).
  *
  * ERRORS.  Every function returns an int status.  0 = SMG_OK.  Negative values
  * are hard errors and leave outputs unspecified; positive values are soft
@@ -181,7 +186,13 @@ int smg_restrict(smg_t h, int fine_level, const double* ru, const double* rp,
 int smg_prolong_add(smg_t h, int fine_level, const double* zcu, const double* zcp,
                     double* u, double* p, smg_stream_t s);
 
-/* Exact solve on level 0 with the bordered matrix (mean-free pressure result). */
+/* Exact solve on level 0 (Section 3: the coarsest level of the iterate is
+ * solved exactly).  The saddle matrix of level 0 is singular on constant
+ * pressures (B^T 1 = 0), so it is bordered by the constraint m^T p = 0,
+ * m_i = int phi_i (Section 1: int p = 0) and a multiplier; its inverse is
+ * formed in FP64 at smg_setup.  z = (zu, zp) receives the solution with a
+ * mean-free pressure; r must be compatible (1^T rp = 0) for z to solve the
+ * unbordered system.  Level-0 layouts; outputs must not alias inputs. */
 int smg_coarse_solve(smg_t h, const double* ru, const double* rp, double* zu, double* zp,
                      smg_stream_t s);
 
@@ -223,8 +234,12 @@ int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* u
                     smg_stream_t s);
 
 /*
- * Solve calA x = F on the finest level to ||F - calA x|| <= rtol ||F|| (2-norm
- * over interior velocity and all pressure entries) by repeated iterates.
+ * Solve calA x = F on the finest level by repeated iterates of the coupled
+ * multigrid method (Section 3, smoothers of Section 4, L of Section 6), each
+ * followed by the mean projection (Section 1: int p = 0), until
+ * ||F - calA x|| <= rtol ||F|| (2-norm over interior velocity and all
+ * pressure entries; the paper's own experiments stop on the error instead,
+ * see smg_solve_error).
  * (u, p) are the initial guess on entry and the solution on return (mean-free
  * pressure).  iters, relres and history (maxit doubles, relative residual
  * after each iterate) may be NULL; they are HOST pointers.  Synchronous.
@@ -236,8 +251,10 @@ int smg_solve(smg_t h, const double* fu, const double* gp, double rtol, int maxi
               smg_stream_t s);
 
 /*
- * Same as smg_solve, but each iterate is one FP32 multigrid cycle applied to
- * the correction equation calA d = r, inside FP64 iterative refinement:
+ * Same as smg_solve, but each iterate is one FP32 multigrid cycle (the iterate
+ * of Section 3 in single precision at every level, an addition beside the
+ * paper's FP64 method) applied to the correction equation calA d = r, inside
+ * FP64 iterative refinement:
  *   r = F - calA x (FP64); d = cycle_fp32(r) from d = 0 with the FP64 coarse
  *   solve; x += d (FP64); pressure mean removed (FP64).
  * iters counts outer refinement steps (= FP32 cycles).  Synchronous.
@@ -251,8 +268,9 @@ int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, in
  * slightly when tau and sigma depend on the level and on beta).  Sets tau and
  * sigma of `level` (-1: every level) of h; they start at smg_params' tau and
  * sigma.  The coarsest level (solved exactly) ignores them.  Captured
- * iterates of h are dropped and captured again by the next solve.  For a
- * hierarchy of a batch use smg_batch_set_damping.  Errors: SMG_EINVAL
+ * iterates of h are dropped and captured again by the next solve; a batch
+ * that holds h (smg_batch_handle) plans and captures its iterates again at
+ * its next solve.  Errors: SMG_EINVAL
  * (values not finite and > 0, bad level).
  */
 int smg_set_damping(smg_t h, int level, double tau, double sigma);
@@ -294,7 +312,9 @@ int smg_dot(smg_t h, int level, int which, const double* a, const double* b, dou
             smg_stream_t s);
 
 /*
- * Batched solves (many independent instances in one set of launches).
+ * Batched solves (many independent instances in one set of launches).  Each
+ * instance runs the iterate of Section 3 on its own problem; batching changes
+ * which launch computes it, not what is computed.
  *
  * A batch holds n hierarchies built as by smg_setup(N[k], beta[k], prm): the
  * sizes may differ (each N[k] = n0 * 2^L_k with the common n0), beta is per
@@ -318,7 +338,8 @@ int smg_batch_size(smg_batch_t b);
 smg_t smg_batch_handle(smg_batch_t b, int k);
 
 /*
- * Solve every instance k to ||F_k - calA_k x_k|| <= rtol ||F_k||.  fu, gp, u,
+ * Solve every instance k to ||F_k - calA_k x_k|| <= rtol ||F_k|| by the
+ * iterates of Section 3, as smg_solve does for one instance.  fu, gp, u,
  * p are HOST arrays of n DEVICE pointers (layouts as for smg_solve of instance
  * k; u[k], p[k] hold the initial guess and receive the solution).  iters,
  * relres, status (host arrays of n, may be NULL) receive the per-instance

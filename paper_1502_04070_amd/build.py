@@ -16,6 +16,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstokesmg.so")
 SOURCES = ["smg_kernels.hip", "smg_fused.hip", "smg_capi.hip"]
+# host-only runtime (no device code): built by the host compiler, the same
+# way the sanitizer check program builds it
+HOST_SOURCES = ["smg_host.cpp"]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# the HIP headers need to know the platform when a plain host compiler reads them
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include")]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 OBJDIR = os.path.join(HERE, "_build")
@@ -33,6 +39,10 @@ def hipcc() -> str:
     return cand
 
 
+def cxx() -> str:
+    return os.environ.get("CXX") or shutil.which("g++") or "c++"
+
+
 def build(verbose: bool = False) -> str:
     """Regenerate the stencil header, compile every translation unit in
     parallel (each launches only kernels it defines, so no relocatable device
@@ -45,6 +55,13 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        objs.append(obj)
+        procs.append((src, subprocess.Popen(cmd)))
+    for src in HOST_SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".host.o")
+        cmd = [cxx(), *HOST_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         objs.append(obj)

@@ -50,9 +50,9 @@ def _set_domain(params, domain):
     """"square": the unit square; "l_shape": the unit square without
     [1/2, 1]^2 (needs an even n0); "union_jack": the unit square on the grid
     of the paper's experiments, the diagonals of the coarsest 2 x 2 grid
-    meeting at the centre (even n0, unfused kernels, no batches).  The lattice
-    layouts are those of the square; entries at points outside the domain are
-    ignored and written zero or left as they were."""
+    meeting at the centre (even n0; fused and unfused kernels, batches).  The
+    lattice layouts are those of the square; entries at points outside the
+    domain are ignored and written zero or left as they were."""
     if domain not in _lib.DOMAINS:
         raise ValueError(f"domain must be one of {list(_lib.DOMAINS)}")
     params.domain = _lib.DOMAINS[domain]
@@ -67,9 +67,10 @@ def _set_schedule(params, schedule):
 
 
 class Hierarchy:
-    """A multigrid hierarchy of the generalized Stokes system on the unit square
-    or the L-shaped domain (uniformly refined same-diagonal grid, Taylor-Hood
-    P2-P1)."""
+    """A multigrid hierarchy of the generalized Stokes system (Taylor-Hood
+    P2-P1, uniformly refined grid): the unit square on the same-diagonal grid,
+    the L-shaped domain on the same grid, or the unit square on the union-jack
+    grid of the paper's experiments (the `domain` argument)."""
 
     def __init__(self, N: int, beta: float, smoother: str = "ne", tau: float | None = None,
                  sigma: float = 0.8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,

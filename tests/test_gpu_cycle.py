@@ -154,10 +154,15 @@ def test_initial_guess_boundary_ignored_and_restart():
 @pytest.mark.parametrize("beta", [1.0, 1e4])
 def test_fp32_cycle_matches_oracle_fp32_cycle(beta, kind):
     """One FP32 cycle from an FP32 iterate against the oracle's FP32 cycle
-    (single precision at every level, coarsest level solved in FP64): the two
-    agree to FP32 rounding (1e-6 of the update; the FP32 cycle itself differs
-    from the FP64 one by about 1e-7 of it), and the GPU result is farther than
-    FP64 rounding from the FP64 cycle, so the GPU cycle does run in FP32."""
+    (single precision at every level, coarsest level solved in FP64).
+
+    Two FP32 implementations with different summation orders (and fused
+    multiply-adds on the GPU) each carry their own rounding error, so they
+    agree to the size of that error, not better: the bar is three times the
+    oracle's own FP32-vs-FP64 deviation, and at least 1e-6 of the update
+    (here 1e-7 .. 2e-6 of it, against 1e-3 or more for a wrong term).  The
+    GPU result must also be farther than FP64 rounding from the FP64 cycle,
+    so the GPU cycle does run in FP32."""
     print(f"fp32 cycle {kind} beta={beta}", flush=True)
     N = 64
     gkw, prm = _params(kind)
@@ -186,7 +191,7 @@ def test_fp32_cycle_matches_oracle_fp32_cycle(beta, kind):
     e64 = np.linalg.norm(gotp - ref64) / upd
     o3264 = np.linalg.norm(ref32 - ref64) / upd
     print(f"  |gpu-oracle32|={e32:.2e} |gpu-oracle64|={e64:.2e} |oracle32-oracle64|={o3264:.2e}", flush=True)
-    assert e32 <= 1e-6, e32
+    assert e32 <= max(1e-6, 3.0 * o3264), (e32, o3264)
     assert e64 >= 1e-9, e64
 
 
