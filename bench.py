@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # together with a hash of the sources the kernel is built from; the figure is
 # reported only while those sources are unchanged.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "ne_step_h128x5_counters.txt")
-NE_KERNEL_SOURCES = ["smg_fused.hip", "smg_fused.h", "smg_cell.h", "smg_internal.h", "gen_stencils.py"]
+NE_KERNEL_SOURCES = ["smg_fused.hip", "smg_fused.h", "smg_cell.h", "smg_stage.h", "smg_internal.h", "gen_stencils.py"]
 
 
 def dofs(N):

@@ -12,6 +12,7 @@
 // velocity space and at vertices outside the grid.
 #pragma once
 #include "smg_internal.h"
+#include "smg_stage.h"
 
 namespace smg {
 #include "stencils.inc"

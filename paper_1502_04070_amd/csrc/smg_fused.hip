@@ -21,6 +21,8 @@
 // intermediate twice (6 vectors); k_ne streams x and F once and writes x once
 // (3 vectors); k_ne2 does two steps for the same three vectors.  k_resid_restrict reads x and F and writes a quarter-size
 // coarse vector instead of writing and re-reading the fine defect.
+#include <type_traits>
+
 #include "smg_cell.h"
 #include "smg_fused.h"
 
@@ -95,6 +97,167 @@ __device__ __forceinline__ T sq_pro_p1(const T* zp, int Nc, int i, int j) {
   }
 }
 
+// The same split in two, so that the loads can be issued with the rest of a
+// window before any is waited for: pro_p1_fetch reads the coarse values the
+// fine vertex (i, j) needs (corners (I, J), (I+1, J), (I, J+1), (I+1, J+1) of
+// its coarse square, zero where unused), pro_p1_value combines them with the
+// same expressions as sq_pro_p1.
+template <class T, int DOM>
+__device__ __forceinline__ void pro_p1_fetch(const T* zp, int Nc, int i, int j, T z[4]) {
+  const int NPc = Nc + 1, I = i >> 1, J = j >> 1;
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int o = uj_orient_c(Nc, I, J), v = 2 * (j & 1) + (i & 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ci = I + (q & 1), cj = J + (q >> 1);
+      z[q] = (smg_stencil::UJ_PP[o][v][q] != 0.0 && ci <= Nc && cj <= Nc) ? zp[(size_t)cj * NPc + ci] : T(0);
+    }
+  } else {
+    z[0] = zp[(size_t)J * NPc + I];
+    z[1] = ((i & 1) && !(j & 1)) ? zp[(size_t)J * NPc + I + 1] : T(0);
+    z[2] = (!(i & 1) && (j & 1)) ? zp[(size_t)(J + 1) * NPc + I] : T(0);
+    z[3] = ((i & 1) && (j & 1)) ? zp[(size_t)(J + 1) * NPc + I + 1] : T(0);
+  }
+}
+
+template <class T, int DOM>
+__device__ __forceinline__ T pro_p1_value(int Nc, int i, int j, const T z[4]) {
+  if constexpr (DOM == SMG_DOM_UNIONJACK) {
+    const int I = i >> 1, J = j >> 1;
+    const int o = uj_orient_c(Nc, I, J), v = 2 * (j & 1) + (i & 1);
+    T r = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ci = I + (q & 1), cj = J + (q >> 1);
+      const double w = smg_stencil::UJ_PP[o][v][q];
+      if (w != 0.0 && ci <= Nc && cj <= Nc) r += T(w) * z[q];
+    }
+    return r;
+  } else {
+    if (!(i & 1) && !(j & 1)) return z[0];
+    if ((i & 1) && !(j & 1)) return T(0.5) * (z[0] + z[1]);
+    if (!(i & 1) && (j & 1)) return T(0.5) * (z[0] + z[2]);
+    return T(0.5) * (z[0] + z[3]);
+  }
+}
+
+// Window of the iterate alone on the same squares, staged.
+template <class T, int TX, int TY, int H, int NT, int DOM>
+struct XWindow {
+  static constexpr int XW = 2 * TX + 4 * H, XH = 2 * TY + 4 * H;
+  static constexpr int XPW = TX + 2 * H, XPH = TY + 2 * H;
+  Staged<XW * XH, NT, 2, T> vel;
+  Staged<XPW * XPH, NT, 1, T> pre;
+  template <class J_>
+  __device__ __forceinline__ void fetch(const J_& J, int i0, int j0, int tid) {
+    const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+    vel.fetch(tid, [&](int e, T* v) {
+      const int a = 2 * i0 - 2 * H + e % XW, b = 2 * j0 - 2 * H + e / XW;
+      const bool in = dom_u(N, DOM, a, b);
+      const size_t g = (size_t)b * M + a;
+      v[0] = in ? J.xu[g] : T(0);
+      v[1] = in ? J.xu[(size_t)M * M + g] : T(0);
+    });
+    pre.fetch(tid, [&](int e, T* v) {
+      const int i = i0 - H + e % XPW, j = j0 - H + e / XPW;
+      v[0] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+    });
+  }
+  __device__ __forceinline__ void put(int tid, T (*U)[XH][XW], T* P) const {
+    vel.put(tid, [&](int e, const T* v) {
+      U[0][e / XW][e % XW] = v[0];
+      U[1][e / XW][e % XW] = v[1];
+    });
+    pre.put(tid, [&](int e, const T* v) { P[e] = v[0]; });
+  }
+};
+
+// Window of the iterate plus the prolongated coarse correction, x + P z, on
+// the same squares (H even).  fetch() requests the fine window and the coarse
+// window of z that covers it; put() writes both to LDS (z to scratch arrays
+// ZU[2][2 CH + 1][2 CW + 1] and ZP[(CH + 1) (CW + 1)] that the caller reuses
+// later); after a barrier add() forms x + P z in the fine window, with the
+// velocity items (coarse square of the window, component, fine row) of four
+// fine points each (the fine row slowest, so that a wave mostly shares one
+// row class) and the pressure items the window's vertices.  The coarse
+// values stay in LDS rather than registers, which keeps the kernels free of
+// spills.
+template <class T, int TX, int TY, int H, int NT, int DOM>
+struct ProWindow {
+  static_assert(H % 2 == 0, "the window starts on a coarse square");
+  static constexpr int CW = TX / 2 + H, CH = TY / 2 + H;       // coarse squares of the window
+  static constexpr int ZW = 2 * CW + 1, ZH = 2 * CH + 1;       // coarse lattice of the window
+  static constexpr int ZPW = CW + 1, ZPH = CH + 1;             // coarse vertices of the window
+  static constexpr int XPW = TX + 2 * H, XPH = TY + 2 * H;
+  XWindow<T, TX, TY, H, NT, DOM> x;
+  Staged<ZW * ZH, NT, 2, T> zv;
+  Staged<ZPW * ZPH, NT, 1, T> zpv;
+  template <class J_>
+  __device__ __forceinline__ void fetch(const J_& J, int i0, int j0, int tid) {
+    x.fetch(J, i0, j0, tid);
+    const int Nc = J.L.N / 2, Mc = 2 * Nc + 1, NPc = Nc + 1;
+    // coarse lattice origin (i0 - H, j0 - H), coarse vertex origin ((i0 - H) / 2, (j0 - H) / 2)
+    zv.fetch(tid, [&](int e, T* v) {
+      const int A = i0 - H + e % ZW, B = j0 - H + e / ZW;
+      const bool in = dom_u(Nc, DOM, A, B);
+      const size_t g = (size_t)B * Mc + A;
+      v[0] = in ? J.zu[g] : T(0);
+      v[1] = in ? J.zu[(size_t)Mc * Mc + g] : T(0);
+    });
+    zpv.fetch(tid, [&](int e, T* v) {
+      const int I = (i0 - H) / 2 + e % ZPW, Jc = (j0 - H) / 2 + e / ZPW;
+      v[0] = (I >= 0 && Jc >= 0 && I <= Nc && Jc <= Nc) ? J.zp[(size_t)Jc * NPc + I] : T(0);
+    });
+  }
+  template <int XW, int XH>
+  __device__ __forceinline__ void put(int tid, T (*U)[XH][XW], T* P, T* ZU, T* ZP) const {
+    x.put(tid, U, P);
+    zv.put(tid, [&](int e, const T* v) {
+      ZU[e] = v[0];
+      ZU[ZW * ZH + e] = v[1];
+    });
+    zpv.put(tid, [&](int e, const T* v) { ZP[e] = v[0]; });
+  }
+  template <int XW, int XH>
+  __device__ __forceinline__ void add(int N, int i0, int j0, int tid, T (*U)[XH][XW], T* P, const T* ZU,
+                                      const T* ZP) const {
+    const int Nc = N / 2;
+    auto interior = [&](int a, int bb) { return dom_u(N, DOM, a, bb); };
+    for (int e = tid; e < CW * CH * 8; e += NT) {
+      const int rb = e / (2 * CW * CH), rem = e % (2 * CW * CH);
+      const int c = rem / (CW * CH), cell = rem % (CW * CH);
+      const int ci = cell % CW, cj = cell / CW;
+      const int I = i0 / 2 - H / 2 + ci, Jc = j0 / 2 - H / 2 + cj;
+      const T* zc = ZU + c * ZW * ZH + (2 * cj) * ZW + 2 * ci;
+      auto Z = [&](int dA, int dB) -> T { return zc[dB * ZW + dA]; };
+      const int b = 4 * Jc + rb;
+      T* row = &U[c][4 * cj + rb][4 * ci];
+      T w[4] = {row[0], row[1], row[2], row[3]};
+      switch (rb) {
+#define SMG_ROW(RB)                                                              \
+  case RB:                                                                       \
+    if (interior(4 * I + 0, b)) w[0] += sq_pro<0, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 1, b)) w[1] += sq_pro<1, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 2, b)) w[2] += sq_pro<2, RB, T, DOM>(Nc, I, Jc, Z);    \
+    if (interior(4 * I + 3, b)) w[3] += sq_pro<3, RB, T, DOM>(Nc, I, Jc, Z);    \
+    break;
+        SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
+#undef SMG_ROW
+      }
+#pragma unroll
+      for (int ra = 0; ra < 4; ++ra) row[ra] = w[ra];
+    }
+    for (int e = tid; e < XPW * XPH; e += NT) {
+      const int i = i0 - H + e % XPW, j = j0 - H + e / XPW;
+      if (!dom_p(N, DOM, i, j)) continue;
+      const int li = (i >> 1) - (i0 - H) / 2, lj = (j >> 1) - (j0 - H) / 2;
+      const T z[4] = {ZP[lj * ZPW + li], ZP[lj * ZPW + li + 1], ZP[(lj + 1) * ZPW + li],
+                      ZP[(lj + 1) * ZPW + li + 1]};
+      P[e] += pro_p1_value<T, DOM>(Nc, i, j, z);
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // k_ne: one fused normal-equation step on a TX x TY tile of squares
 // ---------------------------------------------------------------------------
@@ -143,71 +306,22 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
     if (tid >= TX * TY && i <= N && j <= N) s2 = J.L.sinv[(size_t)j * NP + i];
   }
 
-  // ---- stage 0: the iterate on the tile plus two squares of halo
+  // ---- stage 0: the iterate (plus the prolongated coarse correction with
+  // PRO) on the tile plus two squares of halo, every load in flight at once
   if constexpr (!ZG) {
     if constexpr (PRO) {
-      // one work item per (coarse square of the window, component, fine row):
-      // four fine points each
-      constexpr int CW = TX / 2 + 2, CH = TY / 2 + 2;
-      const int Nc = N / 2, Mc = 2 * Nc + 1;
-      for (int e = tid; e < CW * CH * 8; e += NT) {
-        // fine row slowest, so that a wave mostly shares one row class
-        const int rb = e / (2 * CW * CH), rem = e % (2 * CW * CH);
-        const int c = rem / (CW * CH), cell = rem % (CW * CH);
-        const int ci = cell % CW, cj = cell / CW;
-        const int I = i0 / 2 - 1 + ci, Jc = j0 / 2 - 1 + cj;
-        T z[3][3];
-#pragma unroll
-        for (int dB = 0; dB < 3; ++dB)
-#pragma unroll
-          for (int dA = 0; dA < 3; ++dA) {
-            const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = dom_u(Nc, DOM, A, B)
-                            ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
-          }
-        auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
-        const int b = 4 * Jc + rb;
-        T v[4];
-#pragma unroll
-        for (int ra = 0; ra < 4; ++ra) {
-          const int a = 4 * I + ra;
-          v[ra] = interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
-        }
-        switch (rb) {
-#define SMG_ROW(RB)                                                              \
-  case RB:                                                                       \
-    if (interior(4 * I + 0, b)) v[0] += sq_pro<0, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 1, b)) v[1] += sq_pro<1, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 2, b)) v[2] += sq_pro<2, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 3, b)) v[3] += sq_pro<3, RB, T, DOM>(Nc, I, Jc, Z);    \
-    break;
-          SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
-#undef SMG_ROW
-        }
-#pragma unroll
-        for (int ra = 0; ra < 4; ++ra) sx[c][4 * cj + rb][4 * ci + ra] = v[ra];
-      }
-      for (int e = tid; e < XPW * XPH; e += NT) {
-        const int li = e % XPW, lj = e / XPW;
-        const int i = i0 - 2 + li, j = j0 - 2 + lj;
-        T v = T(0);
-        if (dom_p(N, DOM, i, j)) v = J.xp[(size_t)j * NP + i] + sq_pro_p1<T, DOM>(J.zp, N / 2, i, j);
-        sxp[e] = v;
-      }
+      // the coarse window of z goes to the storage of y (written in stage 1)
+      using PW = ProWindow<T, TX, TY, 2, NT, DOM>;
+      static_assert(2 * PW::ZW * PW::ZH <= 2 * YH * YW && PW::ZPW * PW::ZPH <= YPH * YPW, "z window fits");
+      PW w;
+      w.fetch(J, i0, j0, tid);
+      w.put(tid, sx, sxp, &sy[0][0][0], syp);
+      __syncthreads();
+      w.add(N, i0, j0, tid, sx, sxp, &sy[0][0][0], syp);
     } else {
-      for (int e = tid; e < XW * XH; e += NT) {
-        const int la = e % XW, lb = e / XW;
-        const int a = 2 * i0 - 4 + la, b = 2 * j0 - 4 + lb;
-        const bool in = interior(a, b);
-        const size_t g = (size_t)b * M + a;
-        sx[0][lb][la] = in ? J.xu[g] : T(0);
-        sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
-      }
-      for (int e = tid; e < XPW * XPH; e += NT) {
-        const int li = e % XPW, lj = e / XPW;
-        const int i = i0 - 2 + li, j = j0 - 2 + lj;
-        sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
-      }
+      XWindow<T, TX, TY, 2, NT, DOM> w;
+      w.fetch(J, i0, j0, tid);
+      w.put(tid, sx, sxp);
     }
     __syncthreads();
   }
@@ -413,80 +527,44 @@ __device__ __forceinline__ void ne2_tile(const NEJob<T>& J, int tile) {
   auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
   auto inside = [&](int i, int j) { return dom_p(N, DOM, i, j); };
 
-  // ---- stage 0: F and Shat^-1 on the tile + 3, the iterate on the tile + 4
+  // ---- stage 0: F and Shat^-1 on the tile + 3, the iterate on the tile + 4,
+  // every load in flight at once
   const int dn = J.done ? *J.done : 0;
-  for (int e = tid; e < W3 * H3; e += NT) {
-    const int la = e % W3, lb = e / W3;
-    const int a = 2 * i0 - 6 + la, b = 2 * j0 - 6 + lb;
+  Staged<W3 * H3, NT, 2, T> fw;
+  Staged<PW3 * PH3, NT, 2, T> fpw;
+  fw.fetch(tid, [&](int e, T* v) {
+    const int a = 2 * i0 - 6 + e % W3, b = 2 * j0 - 6 + e / W3;
     const bool in = interior(a, b);
     const size_t g = (size_t)b * M + a;
-    sf[0][lb][la] = in ? J.fu[g] : T(0);
-    sf[1][lb][la] = in ? J.fu[(size_t)M * M + g] : T(0);
-  }
-  for (int e = tid; e < PW3 * PH3; e += NT) {
+    v[0] = in ? J.fu[g] : T(0);
+    v[1] = in ? J.fu[(size_t)M * M + g] : T(0);
+  });
+  fpw.fetch(tid, [&](int e, T* v) {
     const int i = i0 - 3 + e % PW3, j = j0 - 3 + e / PW3;
     const bool ok = inside(i, j);
-    sfp[e] = ok ? J.fp[(size_t)j * NP + i] : T(0);
-    ss[e] = ok ? J.L.sinv[(size_t)j * NP + i] : T(0);
-  }
+    v[0] = ok ? J.fp[(size_t)j * NP + i] : T(0);
+    v[1] = ok ? J.L.sinv[(size_t)j * NP + i] : T(0);
+  });
+  using PW = ProWindow<T, TX, TY, 4, NT, DOM>;
+  std::conditional_t<PRO, PW, XWindow<T, TX, TY, 4, NT, DOM>> xw;
+  if constexpr (!ZG) xw.fetch(J, i0, j0, tid);
+  fw.put(tid, [&](int e, const T* v) {
+    sf[0][e / W3][e % W3] = v[0];
+    sf[1][e / W3][e % W3] = v[1];
+  });
+  fpw.put(tid, [&](int e, const T* v) {
+    sfp[e] = v[0];
+    ss[e] = v[1];
+  });
   if constexpr (!ZG) {
     if constexpr (PRO) {
-      // x + P z_c: one item per (coarse square of the window, component, fine row)
-      constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4;
-      const int Nc = N / 2, Mc = 2 * Nc + 1;
-      for (int e = tid; e < CW * CH * 8; e += NT) {
-        const int rb = e / (2 * CW * CH), rem = e % (2 * CW * CH);
-        const int c = rem / (CW * CH), cell = rem % (CW * CH);
-        const int ci = cell % CW, cj = cell / CW;
-        const int I = i0 / 2 - 2 + ci, Jc = j0 / 2 - 2 + cj;
-        T z[3][3];
-#pragma unroll
-        for (int dB = 0; dB < 3; ++dB)
-#pragma unroll
-          for (int dA = 0; dA < 3; ++dA) {
-            const int A = 2 * I + dA, B = 2 * Jc + dB;
-            z[dB][dA] = dom_u(Nc, DOM, A, B)
-                            ? J.zu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] : T(0);
-          }
-        auto Z = [&](int dA, int dB) -> T { return z[dB][dA]; };
-        const int b = 4 * Jc + rb;
-        T v[4];
-#pragma unroll
-        for (int ra = 0; ra < 4; ++ra) {
-          const int a = 4 * I + ra;
-          v[ra] = interior(a, b) ? J.xu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
-        }
-        switch (rb) {
-#define SMG_ROW(RB)                                                              \
-  case RB:                                                                       \
-    if (interior(4 * I + 0, b)) v[0] += sq_pro<0, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 1, b)) v[1] += sq_pro<1, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 2, b)) v[2] += sq_pro<2, RB, T, DOM>(Nc, I, Jc, Z);    \
-    if (interior(4 * I + 3, b)) v[3] += sq_pro<3, RB, T, DOM>(Nc, I, Jc, Z);    \
-    break;
-          SMG_ROW(0) SMG_ROW(1) SMG_ROW(2) SMG_ROW(3)
-#undef SMG_ROW
-        }
-#pragma unroll
-        for (int ra = 0; ra < 4; ++ra) sx0[c][4 * cj + rb][4 * ci + ra] = v[ra];
-      }
-      for (int e = tid; e < PW4 * PH4; e += NT) {
-        const int i = i0 - 4 + e % PW4, j = j0 - 4 + e / PW4;
-        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] + sq_pro_p1<T, DOM>(J.zp, N / 2, i, j) : T(0);
-      }
+      // the coarse window of z goes to the storage of Y1 (written in stage 1)
+      static_assert(2 * PW::ZW * PW::ZH <= 2 * H3 * W3 && PW::ZPW * PW::ZPH <= PH3 * PW3, "z window fits");
+      xw.put(tid, sx0, sx0p, &sy[0][0][0], syp);
+      __syncthreads();
+      xw.add(N, i0, j0, tid, sx0, sx0p, &sy[0][0][0], syp);
     } else {
-      for (int e = tid; e < W4 * H4; e += NT) {
-        const int la = e % W4, lb = e / W4;
-        const int a = 2 * i0 - 8 + la, b = 2 * j0 - 8 + lb;
-        const bool in = interior(a, b);
-        const size_t g = (size_t)b * M + a;
-        sx0[0][lb][la] = in ? J.xu[g] : T(0);
-        sx0[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
-      }
-      for (int e = tid; e < PW4 * PH4; e += NT) {
-        const int i = i0 - 4 + e % PW4, j = j0 - 4 + e / PW4;
-        sx0p[e] = inside(i, j) ? J.xp[(size_t)j * NP + i] : T(0);
-      }
+      xw.put(tid, sx0, sx0p);
     }
   }
   __syncthreads();
@@ -719,18 +797,12 @@ __device__ __forceinline__ void uz_tile(const UZJob<T>& J, int tile) {
   const T s2 = act2 ? J.L.sinv[(size_t)vj * NP + vi] : T(0);
 
   if constexpr (!ZG) {
-    for (int e = tid; e < XW * XH; e += NT) {
-      const int la = e % XW, lb = e / XW;
-      const int a = 2 * i0 - 6 + la, b = 2 * j0 - 6 + lb;
-      const bool in = interior(a, b);
-      const size_t g = (size_t)b * M + a;
-      sx[0][lb][la] = in ? J.xu[g] : T(0);
-      sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
-    }
-    for (int e = tid; e < PW * PH; e += NT) {
-      const int i = i0 - 3 + e % PW, j = j0 - 3 + e / PW;
-      sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
-    }
+    // the iterate on the tile plus three squares, every load in flight at once
+    static_assert(XWindow<T, TX, TY, 3, NT, DOM>::XW == XW && XWindow<T, TX, TY, 3, NT, DOM>::XPW == PW,
+                  "window shapes");
+    XWindow<T, TX, TY, 3, NT, DOM> w;
+    w.fetch(J, i0, j0, tid);
+    w.put(tid, sx, sxp);
     __syncthreads();
   }
   if (dn) return;   // uniform across the workgroup
@@ -894,19 +966,25 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
     const bool inp = act && dom_p(N, DOM, i, j);
     f1[it][8] = inp ? J.fp[(size_t)j * NP + i] : T(0);
   }
-  for (int e = tid; e < XW * XW; e += NT) {
-    const int la = e % XW, lb = e / XW;
-    const int a = 4 * I0 - 6 + la, b = 4 * J0 - 6 + lb;
+  // the fine iterate window, every load in flight at once
+  Staged<XW * XW, NT, 2, T> xw;
+  Staged<XPW * XPW, NT, 1, T> xpw;
+  xw.fetch(tid, [&](int e, T* v) {
+    const int a = 4 * I0 - 6 + e % XW, b = 4 * J0 - 6 + e / XW;
     const bool in = interior(a, b);
     const size_t g = (size_t)b * M + a;
-    sx[0][lb][la] = in ? J.xu[g] : T(0);
-    sx[1][lb][la] = in ? J.xu[(size_t)M * M + g] : T(0);
-  }
-  for (int e = tid; e < XPW * XPW; e += NT) {
-    const int li = e % XPW, lj = e / XPW;
-    const int i = 2 * I0 - 3 + li, j = 2 * J0 - 3 + lj;
-    sxp[e] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
-  }
+    v[0] = in ? J.xu[g] : T(0);
+    v[1] = in ? J.xu[(size_t)M * M + g] : T(0);
+  });
+  xpw.fetch(tid, [&](int e, T* v) {
+    const int i = 2 * I0 - 3 + e % XPW, j = 2 * J0 - 3 + e / XPW;
+    v[0] = dom_p(N, DOM, i, j) ? J.xp[(size_t)j * NP + i] : T(0);
+  });
+  xw.put(tid, [&](int e, const T* v) {
+    sx[0][e / XW][e % XW] = v[0];
+    sx[1][e / XW][e % XW] = v[1];
+  });
+  xpw.put(tid, [&](int e, const T* v) { sxp[e] = v[0]; });
   __syncthreads();
   if (dn) return;   // uniform across the workgroup
   // stage 1: fine defect on squares [2 I0 - 2, 2 I0 + 2 TC] per side

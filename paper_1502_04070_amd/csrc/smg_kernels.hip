@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "smg_internal.h"
+#include "smg_stage.h"
 
 namespace smg {
 #include "stencils.inc"
@@ -179,28 +180,36 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   const bool rows_p = (F == 0) ? (J.out_p != nullptr || J.partial != nullptr) : (F & F_ROWS_P) != 0;
   const bool hu = FL::on(F_IN_U, J.in_u);
   const bool hp = rows_u && FL::on(F_IN_P, J.in_p);
-  if (hu) {
-    for (int e = tid; e < WX * WY; e += NT) {
-      const int la = e % WX, lb = e / WX;
-      const int a = 2 * i0 - 2 + la, b = 2 * j0 - 2 + lb;
+  // the input windows, every load in flight at once
+  Staged<WX * WY, NT, 2, T> uw;
+  Staged<PX * PY, NT, 2, T> pw;
+  if (hu)
+    uw.fetch(tid, [&](int e, T* v) {
+      const int a = 2 * i0 - 2 + e % WX, b = 2 * j0 - 2 + e / WX;
       const bool in = dom_u(N, dom, a, b);
       const size_t g = (size_t)b * M + a;
-      su[0][lb][la] = in ? J.in_u[g] : T(0);
-      su[1][lb][la] = in ? J.in_u[(size_t)M * M + g] : T(0);
-    }
-  }
-  if (hp) {
-    for (int e = tid; e < PX * PY; e += NT) {
-      const int li = e % PX, lj = e / PX;
-      const int i = i0 - 1 + li, j = j0 - 1 + lj;
-      T v = T(0);
-      if (dom_p(N, dom, i, j)) {
-        v = J.in_p[(size_t)j * NP + i];
-        if (FL::on(F_PSUB, J.in_p_sub)) v -= J.in_p_sub[(size_t)j * NP + i];
-      }
-      sp[lj][li] = v;
-    }
-  }
+      v[0] = in ? J.in_u[g] : T(0);
+      v[1] = in ? J.in_u[(size_t)M * M + g] : T(0);
+    });
+  if (hp)
+    pw.fetch(tid, [&](int e, T* v) {
+      const int i = i0 - 1 + e % PX, j = j0 - 1 + e / PX;
+      const bool in = dom_p(N, dom, i, j);
+      const bool sub = in && FL::on(F_PSUB, J.in_p_sub);
+      v[0] = in ? J.in_p[(size_t)j * NP + i] : T(0);
+      v[1] = sub ? J.in_p_sub[(size_t)j * NP + i] : T(0);
+    });
+  if (hu)
+    uw.put(tid, [&](int e, const T* v) {
+      su[0][e / WX][e % WX] = v[0];
+      su[1][e / WX][e % WX] = v[1];
+    });
+  if (hp)
+    pw.put(tid, [&](int e, const T* v) {
+      T x = v[0];
+      if (FL::on(F_PSUB, J.in_p_sub)) x -= v[1];
+      sp[e / PX][e % PX] = x;
+    });
   if (hu || hp) __syncthreads();
   const int tx = tid % TX, ty = tid / TX;
   const int i = i0 + tx, j = j0 + ty;
