@@ -411,6 +411,25 @@ int smg_tune(int n, const int* N, const double* beta, const smg_params* base, in
              smg_params* best, double* best_ms, smg_params* tried, double* tried_ms, int cap,
              int* ntried, smg_stream_t s);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * residual of smg_residual on a grid of N x N squares (N in 2..4096; even N
+ * on the L-shaped and union-jack domains) with coefficient beta, without a
+ * hierarchy and without any allocation.  fu, gp, u, p, ru, rp: device
+ * vectors in the lattice layout of that grid (as for smg_residual); norm2
+ * (device, one double, or NULL) receives the squared norm, summed in a
+ * fixed order.  The per-tile partial sums live in a fixed device array of
+ * 2^17 doubles (1 MiB) that each GPU holds until the process ends; a grid
+ * needing more partials than that is refused (SMG_EINVAL).  Every call
+ * rewrites every partial it reads, so no clearing is needed; calls that
+ * overlap in time on one device race on the array.  Stream-ordered.
+ * Errors: SMG_EINVAL, SMG_EHIP.
+ */
+int smg_residual_noalloc(int N, double beta, int domain, const double* fu, const double* gp,
+                         const double* u, const double* p, double* ru, double* rp, double* norm2,
+                         smg_stream_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,7 @@ SIGNATURES = {
                  C.POINTER(D), C.POINTER(SmgParams), C.POINTER(D), I, C.POINTER(I), P],
     "smg_batch_solve": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),
                         C.POINTER(I), C.POINTER(D), C.POINTER(I), P],
+    "smg_residual_noalloc": [I, D, I, P, P, P, P, P, P, P, P],
     "smg_batch_solve_mixed": [P, C.POINTER(P), C.POINTER(P), D, I, C.POINTER(P), C.POINTER(P),
                               C.POINTER(I), C.POINTER(D), C.POINTER(I), P],
 }

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1129,5 +1130,78 @@ int smg_time_kernel(smg_t h, int which, int reps, double* avg_ms, smg_stream_t s
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// The entry point that allocates nothing
+// ===========================================================================
+// Callers that cannot allocate device memory (code under HIP graph capture,
+// tight serving loops) compute a residual and its norm with the per-tile
+// partial sums in `scratch`, a file-scope device array of fixed size: every
+// GPU the library runs on holds its own copy until the process ends.  Its
+// address on a device is looked up once, with that device current, and only
+// that address is ever passed to kernels.  Each call overwrites every partial
+// it reads (one per tile), so nothing has to start at zero; calls that
+// overlap on one device race on the array.
+
+namespace {
+
+constexpr int NOALLOC_SCRATCH_DOUBLES = 1 << 17;   // 1 MiB
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(SMG_EINVAL, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SMG_EHIP, "no address for the scratch array on device %d", dev);
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SMG_OK;
+}
+
+}  // namespace
+
+extern "C" int smg_residual_noalloc(int N, double beta, int domain, const double* fu, const double* gp,
+                                    const double* u, const double* p, double* ru, double* rp, double* norm2,
+                                    smg_stream_t sv) {
+  if (!fu || !gp || !u || !p || !ru || !rp) return fail(SMG_EINVAL, "null vector");
+  if (N < 2 || N > 4096) return fail(SMG_EINVAL, "N=%d outside 2..4096", N);
+  if (domain != SMG_DOM_SQUARE && domain != SMG_DOM_LSHAPE && domain != SMG_DOM_UNIONJACK)
+    return fail(SMG_EINVAL, "unknown domain %d", domain);
+  if (domain != SMG_DOM_SQUARE && N % 2) return fail(SMG_EINVAL, "this domain needs an even N");
+  if (!(beta >= 0) || !std::isfinite(beta)) return fail(SMG_EINVAL, "beta must be finite and >= 0");
+  const int tiles = stencil_tiles(N);
+  if (norm2 && tiles > NOALLOC_SCRATCH_DOUBLES)
+    return fail(SMG_EINVAL, "N=%d needs %d partial sums, the scratch array holds %d", N, tiles,
+                NOALLOC_SCRATCH_DOUBLES);
+  double* part = nullptr;
+  if (norm2) {
+    int rc = noalloc_scratch(&part);
+    if (rc) return rc;
+  }
+  hipStream_t s = (hipStream_t)sv;
+  LevelCoef<double> c64;
+  LevelCoef<float> c32;
+  host::make_coef(N, domain, beta, c64, c32);
+  StencilJob<double> R{};
+  R.L = c64;
+  R.w_u = R.w_p = 1.0;
+  R.in_u = u; R.in_p = p;
+  R.rhs_u = fu; R.rhs_p = gp;
+  R.out_u = ru; R.out_p = rp;
+  R.partial = part;
+  launch_stencil<double>(R, ROWS_UP, s);
+  if (norm2) launch_reduce(part, tiles, norm2, s);
+  return launch_status("smg_residual_noalloc");
+}
 
 #include "smg_batch.inc"

@@ -66,6 +66,27 @@ def _set_schedule(params, schedule):
         setattr(params, k, int(v))
 
 
+def residual_noalloc(N, beta, fu, gp, u, p, domain="square", ru=None, rp=None, norm=False):
+    """r = F - calA x on a grid of N x N squares with coefficient beta, without
+    a hierarchy and without device allocation inside the library (the norm's
+    partial sums use its fixed device scratch array; the caller passes every
+    vector, ru / rp are allocated here only if not given).  Returns (ru, rp)
+    or (ru, rp, norm2) with norm2 a one-element device tensor."""
+    lib = _lib.load()
+    if domain not in _lib.DOMAINS:
+        raise ValueError(f"domain must be one of {list(_lib.DOMAINS)}")
+    M = 2 * int(N) + 1
+    for t, shape in ((fu, (2, M, M)), (gp, (N + 1, N + 1)), (u, (2, M, M)), (p, (N + 1, N + 1))):
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+    ru = torch.empty_like(u) if ru is None else ru
+    rp = torch.empty_like(p) if rp is None else rp
+    n2 = torch.zeros(1, dtype=torch.float64, device=u.device) if norm else None
+    _lib.check(lib.smg_residual_noalloc(int(N), float(beta), _lib.DOMAINS[domain], _ptr(fu), _ptr(gp), _ptr(u),
+                                        _ptr(p), _ptr(ru), _ptr(rp), _ptr(n2), _stream()), "smg_residual_noalloc")
+    return (ru, rp, n2) if norm else (ru, rp)
+
+
 class Hierarchy:
     """A multigrid hierarchy of the generalized Stokes system (Taylor-Hood
     P2-P1, uniformly refined grid): the unit square on the same-diagonal grid,

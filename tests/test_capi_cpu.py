@@ -94,3 +94,22 @@ def test_every_entry_point_rejects_a_null_handle(lib):
         else:
             assert rc == -1, (name, rc)
             assert lib.smg_last_error().decode(), name
+
+
+@pytest.mark.parametrize("N,beta,domain,needle", [
+    (8192, 1.0, 0, "outside 2..4096"),
+    (1, 1.0, 0, "outside 2..4096"),
+    (7, 1.0, 1, "even N"),
+    (7, 1.0, 2, "even N"),
+    (8, -1.0, 0, "beta"),
+    (8, float("inf"), 0, "beta"),
+    (8, 1.0, 4, "domain"),
+])
+def test_residual_noalloc_rejects_bad_arguments(lib, N, beta, domain, needle):
+    """The entry point that allocates nothing checks its sizes before any
+    device call (the pointers are never dereferenced on this path)."""
+    buf = (C.c_double * 4)()
+    ptr = C.cast(buf, C.c_void_p)
+    rc = lib.smg_residual_noalloc(N, beta, domain, ptr, ptr, ptr, ptr, ptr, ptr, ptr, None)
+    assert rc == -1
+    assert needle in lib.smg_last_error().decode()
