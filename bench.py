@@ -628,6 +628,8 @@ def main():
                     help="instances of the probe batch (5: the betas of the main workload)")
     ap.add_argument("--probe-batch64x4", action="store_true",
                     help="only time the finest-level normal-equation step of the 64 x 4 batch (no graphs)")
+    ap.add_argument("--probe-cycle", type=int, default=0, metavar="N",
+                    help="only run single-instance V(2,2) iterates at h=1/N, launched directly (no graphs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--cpu-extras", action="store_true",
@@ -649,6 +651,22 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.probe_cycle:
+        N = args.probe_cycle
+        h = Hierarchy(N, 1.0)
+        F, G = inputs.uniform_f(N, seed=0)
+        fu, gp = h.load(torch.from_numpy(F).cuda(), torch.from_numpy(G).cuda())
+        u, p = h.zeros()
+        h.cycle(fu, gp, u, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.kernel_reps):
+            h.cycle(fu, gp, u, p)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe_cycle": {"N": N, "iterates": args.kernel_reps,
+                                          "ms_per_iterate": 1e3 * (time.perf_counter() - t0) / args.kernel_reps}}),
+              flush=True)
         return
     if args.probe or args.probe_batch64x4:
         if args.probe_batch64x4:
