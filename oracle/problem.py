@@ -31,6 +31,15 @@ def paper_exact_discrete(h: mg.Hierarchy, n=8, split=2):
     return l2_project(h.discs[-1], paper_u, paper_p, n=n, split=split)
 
 
+def paper_exact_on_level(kind: str, k: int, n=8, split=2):
+    """The same x* on level k alone (the finest discretization, no hierarchy):
+    (discretization, x*).  The projection does not depend on beta."""
+    from . import mesh as meshmod
+    from .fem import Discretization
+    disc = Discretization(meshmod.hierarchy(kind, k)[-1])
+    return disc, l2_project(disc, paper_u, paper_p, n=n, split=split)
+
+
 def paper_rate(kind: str, k: int, beta: float, prm: mg.Params, eps: float = 1e-9, maxit: int = 200):
     """(n, q) of the protocol of Section 6 on grid level k."""
     h = mg.Hierarchy(kind, k, beta, n0=2)

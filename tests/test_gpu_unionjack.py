@@ -281,6 +281,28 @@ def test_tables_2_3_on_gpu_against_paper(k):
             assert st == "ok" and _band(n, n_paper), (kind, k, beta, n, n_paper)
 
 
+def test_tables_2_3_level7_with_l2_projected_xstar():
+    """Level 7 (h = 1/256) of Tables 2 (NE W(3,3)) and 3 (Uzawa W(3,3)) for all
+    six beta with the experiment's own x*: the L2 projection of the Section 6
+    fields, computed once by the oracle on the finest level (it does not
+    depend on beta); every count within the band of the paper's."""
+    k, N = 7, 256
+    print("level 7: L2 projection of the Section 6 fields on the host (about a minute)", flush=True)
+    disc, xs = pb.paper_exact_on_level("union_jack", k)
+    us, ps = lat.to_lattice(disc, xs)
+    Us, Ps = dev(us), dev(ps)
+    row = GOLD["table23_levels"].index(k)
+    for ib, beta in enumerate(GOLD["table23_beta"]):
+        for kind, table in (("ne_w33", "table2_ne_3p3"), ("uzawa_w33", "table3_uzawa_3p3")):
+            gkw, _ = _params(kind)
+            gh = gpu_uj(N, beta, **gkw)
+            FU, GP = gh.apply(Us, Ps)
+            _, _, n, q, st = gh.solve_error(FU, GP, Us, Ps)
+            n_paper = GOLD[table][row][ib][0]
+            print(f"  {kind} beta={beta:g}: n={n} q={q:.3f} (paper {n_paper})", flush=True)
+            assert st == "ok" and _band(n, n_paper), (kind, k, beta, n, n_paper)
+
+
 @pytest.mark.parametrize("kind", ["ne", "uzawa_w33"])
 def test_batch_on_union_jack(kind):
     """Uneven union-jack instances (h = 1/8 ... 1/128) in one batch, FP64 and

@@ -198,3 +198,13 @@ def test_level_damping_acts_on_its_own_level():
     # a middle level's value enters the iterate
     y3 = mg.cycle(h3, 2, x0, f, mg.Params(level_tau=(0.35, 0.2, 0.35)))
     assert np.linalg.norm(y3 - y1) > 1e-6 * np.linalg.norm(y1)
+
+
+def test_level_only_exact_solution_equals_hierarchy_one():
+    """x* of Section 6 built on the finest level alone equals the one built
+    through a whole hierarchy (same mesh, same projection)."""
+    from oracle import problem as pb
+    h = mg.Hierarchy("union_jack", 3, 1.0)
+    disc, xs = pb.paper_exact_on_level("union_jack", 3)
+    assert disc.mesh.nt == h.discs[-1].mesh.nt
+    assert np.array_equal(xs, pb.paper_exact_discrete(h))
