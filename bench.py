@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # together with a hash of the sources the kernel is built from; the figure is
 # reported only while those sources are unchanged.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "ne_step_h128x5_counters.txt")
+COUNTER_SUMMARY_H512 = os.path.join(ROOT, "profiles", "ne_step_h512_counters.txt")
+COUNTER_SUMMARY_BATCH = os.path.join(ROOT, "profiles", "ne_step_batch64x4_counters.txt")
 NE_KERNEL_SOURCES = ["smg_fused.hip", "smg_fused.h", "smg_cell.h", "smg_stage.h", "smg_internal.h", "gen_stencils.py"]
 
 
@@ -87,11 +89,11 @@ def ne_kernel_source_hash():
     return hsh.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when
+def counter_traffic(path=COUNTER_SUMMARY):
+    """HBM bytes per launch from a committed counter summary, or None when
     it is missing or was taken from other kernel sources."""
     try:
-        with open(COUNTER_SUMMARY) as fh:
+        with open(path) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -342,7 +344,7 @@ def _batch64x4(Ns, betas, fg, sched):
     # the dominant kernel of this workload: the batched finest-level
     # normal-equation step of all 256 instances, timed with HIP events
     rec["roofline"] = roofline_block("finest-level fused normal-equation step, all 256 instances (k_ne_b)",
-                                     Ns, B.time_kernel(0, reps=50))
+                                     Ns, B.time_kernel(0, reps=50), counter_traffic(COUNTER_SUMMARY_BATCH))
     out["batch_64x4_h32_to_h256"] = rec
     del B, fus, gps, us, ps
     torch.cuda.empty_cache()
@@ -430,7 +432,7 @@ def _x_mixed512():
             from paper_1502_04070_amd import Batch
             B1 = Batch([N], [beta], schedule=sched)
             rec["roofline"] = roofline_block("finest-level fused normal-equation step, h=1/512 (k_ne_b)",
-                                             [N], B1.time_kernel(0, reps=100))
+                                             [N], B1.time_kernel(0, reps=100), counter_traffic(COUNTER_SUMMARY_H512))
             del B1
         del h
     out["mixed_h512"] = rec
