@@ -344,7 +344,24 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
   // two steps per launch where the level uses 8 x 8 tiles
   const int tx = H->ne_tx(L.N);
   const bool pair = ne && H->ne2 && tx == 8;
-  for (int k = 0; k < prm.nu_pre;) {
+  Level& C = H->lv[l - 1];
+  Vec<T> xc = Sel<T>::x(C), fc = Sel<T>::f(C);
+  // from a zero iterate with two pre-smoothing steps: the steps, the defect
+  // and its restriction in one launch
+  const bool fuse_rr = pair && z && prm.nu_pre == 2;
+  if (fuse_rr) {
+    NERRJob<T> J{};
+    J.L = Sel<T>::c(L);
+    J.fu = f.u; J.fp = f.p;
+    J.ou = alt.u; J.op = alt.p;
+    J.cu = fc.u; J.cp = fc.p;
+    J.tau = T(L.tau);
+    J.done = done;
+    launch_ne2rr<T>(J, s);
+    std::swap(cur, alt);
+    z = false;
+  }
+  for (int k = 0; k < prm.nu_pre && !fuse_rr;) {
     if (ne) {
       NEJob<T> J{};
       J.L = Sel<T>::c(L);
@@ -365,9 +382,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     }
     z = false;
   }
-  Level& C = H->lv[l - 1];
-  Vec<T> xc = Sel<T>::x(C), fc = Sel<T>::f(C);
-  {
+  if (!fuse_rr) {
     RRJob<T> R{};
     R.L = Sel<T>::c(L);
     R.xu = cur.u; R.xp = cur.p;

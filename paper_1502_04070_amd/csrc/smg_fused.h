@@ -67,6 +67,28 @@ struct RRJob {
 template <class T>
 void launch_resid_restrict(const RRJob<T>& J, hipStream_t s);
 
+// From a zero iterate: two normal-equation steps and then the defect and its
+// restriction, in one launch (the pre-smoothing of a coarse level with two
+// steps, and the right-hand side of the next coarser level).  Tiles of 4 x 4
+// coarse squares; the fine level N must be even.
+template <class T>
+struct NERRJob {
+  LevelCoef<T> L;     // fine level
+  const T* fu;
+  const T* fp;        // right-hand side of the fine level
+  T* ou;
+  T* op;              // iterate after the two steps (fine level)
+  T* cu;
+  T* cp;              // P^T (F - A x): right-hand side of the coarse level
+  T tau;
+  const int* done;
+};
+int ne2rr_tiles(int Nc);
+template <class T>
+void launch_ne2rr(const NERRJob<T>& J, hipStream_t s);
+template <class T>
+void launch_ne2rr_b(const JobArg<NERRJob<T>>& A, int nb, int dom, hipStream_t s);
+
 // the iterate on levels 0..Lc by one workgroup
 constexpr int CC_MAX_LEVELS = 5;
 enum { CC_NE = 1, CC_UZAWA = 2, CC_RESTRICT = 3, CC_PROLONG = 4, CC_COARSE = 5 };

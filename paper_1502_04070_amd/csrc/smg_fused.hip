@@ -1083,6 +1083,285 @@ template void launch_resid_restrict<double>(const RRJob<double>&, hipStream_t);
 template void launch_resid_restrict<float>(const RRJob<float>&, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// k_ne2rr: from a zero iterate, two normal-equation steps, then the defect
+// and its restriction, on a tile of 4 x 4 coarse squares (8 x 8 fine ones)
+// ---------------------------------------------------------------------------
+// Each stage needs its input on one more square around its own squares, so
+// with the fine tile at [i0, i0 + 8) (i0 = 2 I0) the regions of fine squares
+// are R1 = [-6, 12] for Y1 = L^-1 F, R2 = [-5, 11] for X1 = tau L^-1 A Y1,
+// R3 = [-4, 10] for Y2 = L^-1 (F - A X1), R4 = [-3, 9] for X2 = X1 +
+// tau L^-1 A Y2 and R5 = [-2, 8] for the defect R = F - A X2 (what the
+// transposed embedding reads for the coarse tile), all relative to i0 (and
+// j0).  LDS (64 KB at most): one R1-sized array holds F, then Y1 (in place),
+// then Y2, then R; F is kept on R3 (all the later stages read), Shat^-1 on
+// R2 (every stage from the second reads it at its own vertices), X1 on R2
+// and X2 over it in place (each point of X2 reads X1 at that point only).
+// Every value uses the same expressions as two single steps and the
+// defect-restriction kernel.
+
+template <class T, int DOM>
+__device__ __forceinline__ void ne2rr_tile(const NERRJob<T>& J, int tile) {
+  constexpr int TC = 4, FT = 2 * TC, NT = 256;
+  constexpr int S1 = FT + 11, S2 = FT + 9, S3 = FT + 7, S4 = FT + 5, S5 = FT + 3;
+  constexpr int W1 = 2 * S1, W2 = 2 * S2, W3 = 2 * S3, W5 = 2 * S5;
+  __shared__ T sy[2][W1][W1];      // F, Y1, Y2, R
+  __shared__ T syp[S1 * S1];       // Y1, Y2, R (pressure)
+  __shared__ T sf[2][W3][W3];      // F on R3
+  __shared__ T sfp[S3 * S3];
+  __shared__ T ss[S2 * S2];        // Shat^-1 on R2
+  __shared__ T sx[2][W2][W2];      // X1, X2
+  __shared__ T sxp[S2 * S2];
+  static_assert(sizeof(T) * (2 * W1 * W1 + S1 * S1 + 2 * W3 * W3 + S3 * S3 + 2 * S2 * S2 + 2 * W2 * W2) <= 65536,
+                "LDS of one workgroup");
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int Nc = N / 2, Mc = 2 * Nc + 1, NPc = Nc + 1;
+  const int ntx = (Nc + TC) / TC;
+  const int I0 = (tile % ntx) * TC, J0 = (tile / ntx) * TC;
+  const int i0 = 2 * I0, j0 = 2 * J0;
+  const int tid = threadIdx.x;
+  const T tau = J.tau;
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
+  auto inside = [&](int i, int j) { return dom_p(N, DOM, i, j); };
+
+  // ---- stage 0: F and Shat^-1 on R1, every load in flight at once; Y1's
+  // pressure part L^-1 (F_p - 0) directly
+  const int dn = J.done ? *J.done : 0;
+  Staged<W1 * W1, NT, 2, T> fw;
+  Staged<S1 * S1, NT, 2, T> fpw;
+  fw.fetch(tid, [&](int e, T* v) {
+    const int a = 2 * i0 - 12 + e % W1, b = 2 * j0 - 12 + e / W1;
+    const bool in = interior(a, b);
+    const size_t g = (size_t)b * M + a;
+    v[0] = in ? J.fu[g] : T(0);
+    v[1] = in ? J.fu[(size_t)M * M + g] : T(0);
+  });
+  fpw.fetch(tid, [&](int e, T* v) {
+    const int i = i0 - 6 + e % S1, j = j0 - 6 + e / S1;
+    const bool ok = inside(i, j);
+    v[0] = ok ? J.fp[(size_t)j * NP + i] : T(0);
+    v[1] = ok ? J.L.sinv[(size_t)j * NP + i] : T(0);
+  });
+  fw.put(tid, [&](int e, const T* v) {
+    const int la = e % W1, lb = e / W1;
+    sy[0][lb][la] = v[0];
+    sy[1][lb][la] = v[1];
+    if (la >= 4 && la < 4 + W3 && lb >= 4 && lb < 4 + W3) {
+      sf[0][lb - 4][la - 4] = v[0];
+      sf[1][lb - 4][la - 4] = v[1];
+    }
+  });
+  fpw.put(tid, [&](int e, const T* v) {
+    const int li = e % S1, lj = e / S1;
+    syp[e] = inside(i0 - 6 + li, j0 - 6 + lj) ? v[1] * (v[0] - T(0)) : T(0);
+    if (li >= 2 && li < 2 + S3 && lj >= 2 && lj < 2 + S3) sfp[(lj - 2) * S3 + li - 2] = v[0];
+    if (li >= 1 && li < 1 + S2 && lj >= 1 && lj < 1 + S2) ss[(lj - 1) * S2 + li - 1] = v[1];
+  });
+  __syncthreads();
+  if (dn) return;   // uniform across the workgroup
+
+  // ---- stage 1: Y1 = L^-1 (F - A 0) on R1, in place over F (own points)
+  for (int e = tid; e < S1 * S1; e += NT) {
+    const int ci = e % S1, cj = e / S1;
+    const int i = i0 - 6 + ci, j = j0 - 6 + cj;
+    T y[9], ad[4];
+    auto Z = [&](int, int, int) -> T { return T(0); };
+    auto Zp = [&](int, int) -> T { return T(0); };
+    sq_rows<T, false, false, DOM>(J.L, i, j, Z, Zp, y, ad);
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T& v = sy[c][2 * cj + DB][2 * ci + DA];
+        const T r = v - y[2 * cls + c];
+        v = in ? ad[cls] * r : T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- stage 2: X1 = 0 + tau L^-1 A Y1 on R2
+  for (int e = tid; e < S2 * S2; e += NT) {
+    const int ci = e % S2, cj = e / S2;
+    const int i = i0 - 5 + ci, j = j0 - 5 + cj;
+    T z[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sy[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return syp[(cj + 1 + dj) * S1 + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, z, ad);
+    }
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+      const T d = ad[cls] * tau;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) sx[c][2 * cj + DB][2 * ci + DA] = in ? T(0) + d * z[2 * cls + c] : T(0);
+    }
+    sxp[e] = inside(i, j) ? T(0) + tau * ss[e] * z[8] : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 3: Y2 = L^-1 (F - A X1) on R3, in the storage of Y1 (no longer read)
+  T (*sy2)[W3][W3] = reinterpret_cast<T (*)[W3][W3]>(&sy[0][0][0]);
+  for (int e = tid; e < S3 * S3; e += NT) {
+    const int ci = e % S3, cj = e / S3;
+    const int i = i0 - 4 + ci, j = j0 - 4 + cj;
+    T y[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return sxp[(cj + 1 + dj) * S2 + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
+    }
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const T r = sf[c][2 * cj + DB][2 * ci + DA] - y[2 * cls + c];
+        sy2[c][2 * cj + DB][2 * ci + DA] = in ? ad[cls] * r : T(0);
+      }
+    }
+    syp[e] = inside(i, j) ? ss[(cj + 1) * S2 + ci + 1] * (sfp[e] - y[8]) : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 4: X2 = X1 + tau L^-1 A Y2 on R4, in place over X1; the tile's
+  // own squares go to the output
+  for (int e = tid; e < S4 * S4; e += NT) {
+    const int ci = e % S4, cj = e / S4;
+    const int i = i0 - 3 + ci, j = j0 - 3 + cj;
+    T z[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sy2[c][2 * cj + 2 + db][2 * ci + 2 + da]; };
+      auto PA = [&](int di, int dj) -> T { return syp[(cj + 1 + dj) * S3 + (ci + 1 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, z, ad);
+    }
+    const bool own = ci >= 3 && ci < 3 + FT && cj >= 3 && cj < 3 + FT && i <= N && j <= N;
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i + DA, b = 2 * j + DB;
+      const bool in = interior(a, b);
+      const T d = ad[cls] * tau;
+      T x2[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T& xv = sx[c][2 * cj + 4 + DB][2 * ci + 4 + DA];
+        x2[c] = in ? xv + d * z[2 * cls + c] : T(0);
+        xv = x2[c];
+      }
+      if (own && a <= 2 * N && b <= 2 * N) {
+        const size_t g = (size_t)b * M + a;
+        J.ou[g] = x2[0];
+        J.ou[(size_t)M * M + g] = x2[1];
+      }
+    }
+    const int q2 = (cj + 2) * S2 + ci + 2;
+    const T x2p = sxp[q2] + tau * ss[q2] * z[8];
+    sxp[q2] = x2p;
+    if (own) J.op[(size_t)j * NP + i] = x2p;
+  }
+  __syncthreads();
+
+  // ---- stage 5: R = F - A X2 on R5, in the storage of Y1 (Y2 no longer read)
+  T (*sr)[W5][W5] = reinterpret_cast<T (*)[W5][W5]>(&sy[0][0][0]);
+  for (int e = tid; e < S5 * S5; e += NT) {
+    const int ci = e % S5, cj = e / S5;
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    T y[9], ad[4];
+    {
+      auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * cj + 6 + db][2 * ci + 6 + da]; };
+      auto PA = [&](int di, int dj) -> T { return sxp[(cj + 3 + dj) * S2 + (ci + 3 + di)]; };
+      sq_rows<T, true, true, DOM>(J.L, i, j, UA, PA, y, ad);
+    }
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const bool in = interior(2 * i + DA, 2 * j + DB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        sr[c][2 * cj + DB][2 * ci + DA] = in ? sf[c][2 * cj + 4 + DB][2 * ci + 4 + DA] - y[2 * cls + c] : T(0);
+    }
+    syp[e] = inside(i, j) ? sfp[(cj + 2) * S3 + ci + 2] - y[8] : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 6: F_c = P^T R on the coarse tile: one wave per coarse node
+  // class, one lane per coarse square
+  const int cls = tid >> 6, q = tid & 63;
+  const int tx = q % TC, ty = q / TC;
+  const int I = I0 + tx, Jc = J0 + ty;
+  if (q < TC * TC && I <= Nc && Jc <= Nc) {
+    const int CA = cls & 1, CB = cls >> 1;
+    const int A = 2 * I + CA, B = 2 * Jc + CB;
+    if (A <= 2 * Nc && B <= 2 * Nc) {
+      const bool in = dom_u(Nc, DOM, A, B);
+      const int la = 4 * tx + 2 * CA + 4, lb = 4 * ty + 2 * CB + 4;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        auto R = [&](int fa, int fb) -> T { return sr[c][lb + fb][la + fa]; };
+        T v = T(0);
+        if (in) {
+          switch (cls) {
+            case 0: v = sq_res<0, T, DOM>(Nc, I, Jc, R); break;
+            case 1: v = sq_res<1, T, DOM>(Nc, I, Jc, R); break;
+            case 2: v = sq_res<2, T, DOM>(Nc, I, Jc, R); break;
+            default: v = sq_res<3, T, DOM>(Nc, I, Jc, R); break;
+          }
+        }
+        J.cu[(size_t)c * Mc * Mc + (size_t)B * Mc + A] = v;
+      }
+    }
+    if (cls == 3) {
+      auto Rp = [&](int di, int dj) -> T { return syp[(2 * ty + 2 + dj) * S5 + (2 * tx + 2 + di)]; };
+      J.cp[(size_t)Jc * NPc + I] = dom_p(Nc, DOM, I, Jc) ? sq_resp<T, DOM>(Nc, I, Jc, Rp) : T(0);
+    }
+  }
+}
+
+template <class T, int DOM>
+__global__ __launch_bounds__(256) void k_ne2rr(NERRJob<T> J) {
+  ne2rr_tile<T, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class T, bool PACK, int DOM>
+__global__ __launch_bounds__(256) void k_ne2rr_b(const JobArg<NERRJob<T>> A) {
+  int tile;
+  const NERRJob<T> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  ne2rr_tile<T, DOM>(J, tile);
+}
+
+int ne2rr_tiles(int Nc) { return ((Nc + 4) / 4) * ((Nc + 4) / 4); }
+
+template <class T>
+void launch_ne2rr(const NERRJob<T>& J, hipStream_t s) {
+  const int nb = ne2rr_tiles(J.L.N / 2);
+  if (J.L.dom == SMG_DOM_LSHAPE) k_ne2rr<T, SMG_DOM_LSHAPE><<<nb, 256, 0, s>>>(J);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) k_ne2rr<T, SMG_DOM_UNIONJACK><<<nb, 256, 0, s>>>(J);
+  else k_ne2rr<T, SMG_DOM_SQUARE><<<nb, 256, 0, s>>>(J);
+}
+template void launch_ne2rr<double>(const NERRJob<double>&, hipStream_t);
+template void launch_ne2rr<float>(const NERRJob<float>&, hipStream_t);
+
+template <class T, int DOM>
+static void launch_ne2rr_b_dom(const JobArg<NERRJob<T>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_ne2rr_b<T, true, DOM><<<nb, 256, 0, s>>>(A);
+  else k_ne2rr_b<T, false, DOM><<<nb, 256, 0, s>>>(A);
+}
+
+template <class T>
+void launch_ne2rr_b(const JobArg<NERRJob<T>>& A, int nb, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_ne2rr_b_dom<T, SMG_DOM_LSHAPE>(A, nb, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_ne2rr_b_dom<T, SMG_DOM_UNIONJACK>(A, nb, s);
+  else launch_ne2rr_b_dom<T, SMG_DOM_SQUARE>(A, nb, s);
+}
+template void launch_ne2rr_b<double>(const JobArg<NERRJob<double>>&, int, int, hipStream_t);
+template void launch_ne2rr_b<float>(const JobArg<NERRJob<float>>&, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
 #include "smg_coarse.inc"
 
 // 12 waves: the nine item types of a phase on the levels up to N = 8 fit in
