@@ -237,6 +237,29 @@ def cpu_extras():
     return out
 
 
+def trace_gaps(path):
+    """Per-iterate figures of the last solve in a kernel trace of
+    --probe-iterate: each iterate ends with the projection/check kernel;
+    `busy` is the summed duration of the iterate's kernels, `span` the time
+    from the end of the previous iterate to the end of this one, and the
+    difference the time the GPU spends between the kernels of the graph."""
+    import csv
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    ends = [k for k, r in enumerate(rows) if "k_pc_b" in r["Kernel_Name"]]
+    last = ends[-20:]
+    per = []
+    for a, b in zip(last[:-1], last[1:]):
+        ks = rows[a + 1:b + 1]
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in ks)
+        span = int(rows[b]["End_Timestamp"]) - int(rows[a]["End_Timestamp"])
+        per.append((len(ks), busy, span))
+    per.sort(key=lambda t: t[2])
+    n, busy, span = per[len(per) // 2]
+    return {"iterates_used": len(per), "kernels_per_iterate": n, "median_span_us": span / 1e3,
+            "busy_us_of_that_iterate": busy / 1e3, "between_kernels_us": (span - busy) / 1e3,
+            "between_kernels_per_launch_us": (span - busy) / 1e3 / n}
+
+
 def copy_calibration(mib=512, reps=5):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the reference
     kernel against which the HBM byte counters are scaled (it reads and writes
@@ -632,6 +655,10 @@ def main():
                     help="instances of the probe batch (5: the betas of the main workload)")
     ap.add_argument("--probe-batch64x4", action="store_true",
                     help="only time the finest-level normal-equation step of the 64 x 4 batch (no graphs)")
+    ap.add_argument("--probe-iterate", choices=["h128x5", "batch64x4"], default=None,
+                    help="only run 20 batched iterates with every instance active (tolerance 0), for a kernel trace")
+    ap.add_argument("--trace-gaps", metavar="CSV", default=None,
+                    help="only summarise a rocprofv3 kernel trace of --probe-iterate: per-iterate kernel time and span")
     ap.add_argument("--probe-cycle", type=int, default=0, metavar="N",
                     help="only run single-instance V(2,2) iterates at h=1/N, launched directly (no graphs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -641,6 +668,9 @@ def main():
     args = ap.parse_args()
     if args.cpu_extras:
         print(json.dumps({"cpu_extras": cpu_extras()}), flush=True)
+        return
+    if args.trace_gaps:
+        print(json.dumps({"trace_gaps": trace_gaps(args.trace_gaps)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
@@ -655,6 +685,33 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.probe_iterate:
+        from paper_1502_04070_amd import tune
+        if args.probe_iterate == "h128x5":
+            Ns, betas = [N_GRID] * len(BETAS), BETAS
+            fg = [inputs.uniform_f(N_GRID, seed=0)] * len(BETAS)
+        else:
+            insts = inputs.batched_instances()
+            Ns = [N for N, _, rhs in insts for _ in rhs]
+            betas = [b for _, b, rhs in insts for _ in rhs]
+            fg = [(F, G) for _, _, rhs in insts for F, G in rhs]
+        sched, _ = tune.schedule_for(Ns, betas, iters=5)
+        B = Batch(Ns, betas, schedule=sched)
+        fus, gps = [], []
+        for h, (F, G) in zip(B.instances, fg):
+            Gd = torch.from_numpy(G).cuda()
+            h.project_mean(Gd)
+            fu, gp = h.load(torch.from_numpy(F).cuda(), Gd)
+            fus.append(fu)
+            gps.append(gp)
+        B.solve(fus, gps, rtol=0.0, maxit=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.solve(fus, gps, rtol=0.0, maxit=20)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe_iterate": {"workload": args.probe_iterate, "schedule": sched, "iterates": 20,
+                                            "ms_per_iterate": 1e3 * (time.perf_counter() - t0) / 20}}), flush=True)
         return
     if args.probe_cycle:
         N = args.probe_cycle
