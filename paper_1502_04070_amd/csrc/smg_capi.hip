@@ -17,6 +17,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "smg_fused.h"
@@ -325,8 +326,12 @@ void uzawa_fused(Level& L, Vec<T> cur, Vec<T> f, Vec<T> alt, bool zg, const int*
   launch_uz<T>(J, zg, s);
 }
 
+// With acc_u / acc_p (FP32 cycles on the finest level), a last smoothing
+// step that is a single fused NE launch adds its result to those FP64
+// vectors instead of writing it; the return value then has null pointers.
 template <class T>
-Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s,
+                   double* acc_u = nullptr, double* acc_p = nullptr) {
   if (l <= H->Lc) {
     coarse_cycle<T>(H, x, f, zg, done, s);
     return x;
@@ -396,6 +401,7 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     zc = cycle_fused<T>(H, l - 1, zc, fc, g == 0, done, s);
   }
   int post = prm.nu_post;
+  bool accd = false;
   if (ne && post > 0) {
     NEJob<T> J{};
     J.L = Sel<T>::c(L);
@@ -406,6 +412,10 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
     J.tau = T(L.tau);
     J.done = done;
     const bool two = pair && post >= 2;
+    if (acc_u && !two && post == 1) {
+      J.acc_u = acc_u; J.acc_p = acc_p;
+      accd = true;
+    }
     if (two) launch_ne2<T>(J, false, true, s);
     else launch_ne<T>(J, false, true, tx, s);
     std::swap(cur, alt);
@@ -423,6 +433,10 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       J.tau = T(L.tau);
       J.done = done;
       const bool two = pair && k + 1 < post;
+      if (acc_u && !two && k + 1 == post) {
+        J.acc_u = acc_u; J.acc_p = acc_p;
+        accd = true;
+      }
       if (two) launch_ne2<T>(J, false, false, s);
       else launch_ne<T>(J, false, false, tx, s);
       std::swap(cur, alt);
@@ -433,32 +447,40 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
       ++k;
     }
   }
+  if (accd) return Vec<T>{nullptr, nullptr};
   return cur;
 }
 
-// iterate on the finest level with the result in x
+// iterate on the finest level with the result in x; with acc_u / acc_p the
+// result may instead have been added to those vectors (returns true then)
 template <class T>
-void top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s) {
+bool top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s,
+               double* acc_u = nullptr, double* acc_p = nullptr) {
   if (!H->fused) {
     if (zg) fill_vec<T>(H->lv[H->L], x, s);
     cycle_rec<T>(H, H->L, x, f, false, done, s);
-    return;
+    return false;
   }
-  Vec<T> r = cycle_fused<T>(H, H->L, x, f, zg, done, s);
+  Vec<T> r = cycle_fused<T>(H, H->L, x, f, zg, done, s, acc_u, acc_p);
+  if (!r.u) return true;
   if (r.u != x.u) copy_vec<T>(H->lv[H->L], x, r, done, s);
+  return false;
 }
 
 void project_mean(smg_hier* H, int l, double* p, const int* done, hipStream_t s) {
   launch_project_mean(H->lv[l].N, H->dom, p, H->red, done, s);
 }
 
-// residual of the finest level: optional write, partial sums in L.partial
+// residual of the finest level: optional write (FP64, or rounded to FP32
+// with r32u / r32p), partial sums in L.partial
 void top_residual(Level& L, const double* xu, const double* xp, const double* fu, const double* fp,
-                  double* ru, double* rp, const int* done, hipStream_t s) {
+                  double* ru, double* rp, const int* done, hipStream_t s, float* r32u = nullptr,
+                  float* r32p = nullptr) {
   StencilJob<double> R = job_of<double>(L);
   R.in_u = xu; R.in_p = xp;
   R.rhs_u = fu; R.rhs_p = fp;
   R.out_u = ru; R.out_p = rp;
+  R.out32_u = r32u; R.out32_p = r32p;
   R.partial = L.partial;
   R.done = done;
   launch_stencil<double>(R, ROWS_UP, s);
@@ -466,12 +488,12 @@ void top_residual(Level& L, const double* xu, const double* xp, const double* fu
 
 // end of an iterate: residual norm and pressure-mean pieces of x in one pass,
 // mean projection, convergence test (the residual is blind to the mean)
-void finish_iter(smg_hier* H, double* ru, double* rp, const int* done, hipStream_t s) {
+void finish_iter(smg_hier* H, float* r32u, float* r32p, const int* done, hipStream_t s) {
   Level& T = H->lv[H->L];
   StencilJob<double> R = job_of<double>(T);
   R.in_u = T.x.u; R.in_p = T.x.p;
   R.rhs_u = T.f.u; R.rhs_p = T.f.p;
-  R.out_u = ru; R.out_p = rp;
+  R.out32_u = r32u; R.out32_p = r32p;
   R.partial = T.partial;
   R.mean_partial = H->mpart;
   R.done = done;
@@ -488,13 +510,15 @@ void enqueue_iter64(smg_hier* H, hipStream_t s) {
 }
 
 // one refinement step: d = cycle_fp32(r), x += d, r = F - calA x, project, test
+// (the FP32 right-hand side, the FP64 residual rounded, is written by the
+// residual pass of the solve's set-up or of the previous step; the cycle's
+// last smoothing step adds its result to x where it is a single NE launch)
 void enqueue_iter_mixed(smg_hier* H, hipStream_t s) {
   Level& T = H->lv[H->L];
   const int* done = &H->st->done;
-  launch_cast_f64_f32(T.t.u, T.f32.u, T.n_u + T.n_p, done, s);
-  top_cycle<float>(H, T.x32, T.f32, true, done, s);
-  launch_axpy_f32(T.x.u, T.x32.u, T.n_u + T.n_p, done, s);
-  finish_iter(H, T.t.u, T.t.p, done, s);
+  if (!top_cycle<float>(H, T.x32, T.f32, true, done, s, T.x.u, T.x.p))
+    launch_axpy_f32(T.x.u, T.x32.u, T.n_u + T.n_p, done, s);
+  finish_iter(H, T.f32.u, T.f32.p, done, s);
 }
 
 // forget the captured iterates of one hierarchy (their launches carry values
@@ -580,8 +604,8 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
   HIPCHK(hipMemcpyAsync(H->st, H->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
   launch_dot(T.N, H->dom, 0, T.f.u, T.f.u, H->red, H->fdots, s);
   launch_dot(T.N, H->dom, 1, T.f.p, T.f.p, H->red, H->fdots + 1, s);
-  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, mixed ? T.t.u : nullptr, mixed ? T.t.p : nullptr,
-               nullptr, s);
+  top_residual(T, T.x.u, T.x.p, T.f.u, T.f.p, nullptr, nullptr, nullptr, s, mixed ? T.f32.u : nullptr,
+               mixed ? T.f32.p : nullptr);
   launch_init_state(T.partial, T.ntiles, H->fdots, H->st, s);
   launch_psum(T.N, H->dom, T.f.p, H->red, H->enorm, s);
   int rc = launch_status("solve init");
@@ -603,7 +627,9 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
     // predict the remaining iterates from the observed rate
     double q = (rel > 0 && rel_prev > 0 && rel < rel_prev) ? std::pow(rel / rel_prev, 1.0 / k) : 0.9;
     q = std::min(std::max(q, 1e-3), 0.99);
-    const double need = (rel > rtol && rtol > 0) ? std::log(rtol / rel) / std::log(q) : 1.0;
+    // rtol = 0 asks for maxit iterates: launch the rest without host checks
+    const double need = rtol > 0 ? (rel > rtol ? std::log(rtol / rel) / std::log(q) : 1.0)
+                                 : (double)(maxit - launched);
     chunk = (int)std::min(64.0, std::max(1.0, std::ceil(need)));
     rel_prev = rel;
   }

@@ -19,6 +19,8 @@ struct NEJob {
   T tau;
   double* partial;    // per tile: ||F - A x||^2 over the owned rows, or NULL
   const int* done;
+  double* acc_u;      // FP32 steps only: if set, the new iterate is added to
+  double* acc_p;      // these FP64 vectors instead of being written to ou / op
 };
 TileShape ne_tile_shape(int N);
 

@@ -380,6 +380,16 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
           x1 = sx[1][2 * ty + 4 + DB][2 * tx + 4 + DA];
         }
         const T d = ad * tau;
+        if constexpr (std::is_same<T, float>::value) {
+          if (J.acc_u) {
+            // x64 += the new FP32 iterate (zero off the domain: nothing to add)
+            if (in) {
+              J.acc_u[g] += (double)(x0 + d * z0);
+              J.acc_u[(size_t)M * M + g] += (double)(x1 + d * z1);
+            }
+            return;
+          }
+        }
         J.ou[g] = in ? x0 + d * z0 : T(0);
         J.ou[(size_t)M * M + g] = in ? x1 + d * z1 : T(0);
       };
@@ -398,7 +408,12 @@ __device__ __forceinline__ void ne_tile(const NEJob<T>& J, int tile) {
         const size_t g = (size_t)j * NP + i;
         T xo = T(0);
         if constexpr (!ZG) xo = sxp[(ty + 2) * XPW + tx + 2];
-        J.op[g] = xo + tau * s2 * zp;
+        if constexpr (std::is_same<T, float>::value) {
+          if (J.acc_p) J.acc_p[g] += (double)(xo + tau * s2 * zp);
+          else J.op[g] = xo + tau * s2 * zp;
+        } else {
+          J.op[g] = xo + tau * s2 * zp;
+        }
       }
     }
   }
@@ -1472,10 +1487,17 @@ void launch_project_partials(const double* mpart, int np, int N, int dom, double
   k_project_partials<<<(n + 1023) / 1024, 256, 0, s>>>(mpart, np, N, dom, p, done);
 }
 
+// pressure entries per thread of the projection / check kernels: on large
+// grids 16, so that few workgroups take a ticket from the one shared counter
+// (each ticket is an atomic on the same word); on small grids 4, so that the
+// work spreads over more workgroups
+__host__ __device__ inline int pc_per_thread(int N) { return N >= 256 ? 16 : 4; }
+
 // Mean projection by every workgroup, then the convergence test by the last
 // workgroup to finish (it is last, so every other workgroup has already read
 // the flag it is about to set).  The residual pieces are reduced in a fixed
 // order, so the test is deterministic.
+template <int PER>
 __device__ __forceinline__ void project_check_body(const double* __restrict__ mpart,
                                                    const double* __restrict__ rpart, int np, int N,
                                                    int dom, double* p, SolveState* st, double* hist,
@@ -1483,23 +1505,53 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   __shared__ double red[4];
   __shared__ double sh_mean;
   __shared__ int sh_last;
-  // every global read of the block is issued before the first reduction:
-  // both sets of tile partials and the block's part of p
+  // every global read of the block is issued before the first wait: the done
+  // flag, both sets of tile partials, the block's part of p and the state the
+  // last workgroup updates (only the last workgroup of this launch writes it,
+  // after every workgroup has passed its reads)
+  const int done = st->done;
+  double fn2 = 0.0, tl2 = 0.0;
+  int its = 0, mxit = 0;
+  if (threadIdx.x == 0) {
+    fn2 = st->fnorm2;
+    tl2 = st->tol2;
+    its = st->iters;
+    mxit = st->maxit;
+  }
+  // the tile partials in chunks of eight rounds, each chunk's loads issued
+  // together; a thread still adds its partials k = tid, tid + 256, ... in
+  // increasing order, so every workgroup forms the same sums
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int k = threadIdx.x; k < np; k += 256) {
-    s1 += mpart[2 * k];
-    s2 += mpart[2 * k + 1];
-    s3 += rpart[k];
+  for (int k0 = threadIdx.x; k0 < np; k0 += 8 * 256) {
+    double a[8], b[8], c[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int k = k0 + r * 256;
+      const bool ok = k < np;
+      a[r] = ok ? mpart[2 * k] : 0.0;
+      b[r] = ok ? mpart[2 * k + 1] : 0.0;
+      c[r] = ok ? rpart[k] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (k0 + r * 256 < np) {
+        s1 += a[r];
+        s2 += b[r];
+        s3 += c[r];
+      }
+    }
   }
   const int n = (N + 1) * (N + 1);
-  double pv[4];
-  bool in[4];
+  constexpr int BLOCK = PER * 256;
+  double pv[PER];
+  bool in[PER];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int e = blk * 1024 + k * 256 + threadIdx.x;
-    in[k] = e < n && dom_p(N, dom, e % (N + 1), e / (N + 1));
+  for (int k = 0; k < PER; ++k) {
+    const int e = blk * BLOCK + k * 256 + threadIdx.x;
+    in[k] = e < n && (dom == SMG_DOM_SQUARE || dom_p(N, dom, e % (N + 1), e / (N + 1)));
     pv[k] = in[k] ? p[e] : 0.0;
   }
+  if (done) return;   // the same value in every thread of the block
   const double t1 = wg_sum<256>(s1, red);
   __syncthreads();
   const double t2 = wg_sum<256>(s2, red);
@@ -1507,11 +1559,13 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   __syncthreads();
   const double m = sh_mean;
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (in[k]) p[blk * 1024 + k * 256 + threadIdx.x] = pv[k] - m;
+  for (int k = 0; k < PER; ++k)
+    if (in[k]) p[blk * BLOCK + k * 256 + threadIdx.x] = pv[k] - m;
   __syncthreads();
+  // No fence before the ticket: the last workgroup reads nothing that the
+  // others write in this launch (only the partials of the previous launch);
+  // the ticket only orders their reads of the done flag before its write.
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned ticket = atomicAdd(&st->arrive, 1u);
     sh_last = (ticket == (unsigned)nblk - 1) ? 1 : 0;
   }
@@ -1519,27 +1573,30 @@ __device__ __forceinline__ void project_check_body(const double* __restrict__ mp
   if (!sh_last) return;
   const double r2 = wg_sum<256>(s3, red);
   if (threadIdx.x == 0) {
-    const double rel = sqrt(r2 / st->fnorm2);
-    const int it = st->iters + 1;
+    const double rel = sqrt(r2 / fn2);
+    const int it = its + 1;
     st->relres = rel;
     st->iters = it;
     if (hist) hist[it - 1] = rel;
     st->arrive = 0u;
     if (!(rel == rel) || rel > 1e300) st->done = 3;
-    else if (r2 <= st->tol2 * st->fnorm2) st->done = 1;
+    else if (r2 <= tl2 * fn2) st->done = 1;
     else if (rel > 1e6) st->done = 2;
-    else if (it >= st->maxit) st->done = 4;
+    else if (it >= mxit) st->done = 4;
   }
 }
 
 __global__ __launch_bounds__(256) void k_project_check(const double* __restrict__ mpart,
                                                        const double* __restrict__ rpart, int np, int N,
                                                        int dom, double* p, SolveState* st, double* hist) {
-  if (st->done) return;
-  project_check_body(mpart, rpart, np, N, dom, p, st, hist, blockIdx.x, gridDim.x);
+  if (pc_per_thread(N) == 16) project_check_body<16>(mpart, rpart, np, N, dom, p, st, hist, blockIdx.x, gridDim.x);
+  else project_check_body<4>(mpart, rpart, np, N, dom, p, st, hist, blockIdx.x, gridDim.x);
 }
 
-__host__ __device__ int pc_blocks(int N) { return ((N + 1) * (N + 1) + 1023) / 1024; }
+__host__ __device__ int pc_blocks(int N) {
+  const int block = pc_per_thread(N) * 256;
+  return ((N + 1) * (N + 1) + block - 1) / block;
+}
 
 void launch_project_check(const double* mpart, const double* rpart, int np, int N, int dom, double* p,
                           SolveState* st, double* hist, hipStream_t s) {
@@ -1550,8 +1607,10 @@ template <bool PACK>
 __global__ __launch_bounds__(256) void k_pc_b(const JobArg<PCJob> A) {
   int tile;
   const PCJob J = block_job<PACK>(A, (int)blockIdx.x, tile);
-  if (J.st->done) return;
-  project_check_body(J.mpart, J.rpart, J.np, J.N, J.dom, J.p, J.st, J.hist, tile, pc_blocks(J.N));
+  if (pc_per_thread(J.N) == 16)
+    project_check_body<16>(J.mpart, J.rpart, J.np, J.N, J.dom, J.p, J.st, J.hist, tile, pc_blocks(J.N));
+  else
+    project_check_body<4>(J.mpart, J.rpart, J.np, J.N, J.dom, J.p, J.st, J.hist, tile, pc_blocks(J.N));
 }
 
 void launch_pc_b(const JobArg<PCJob>& A, int nb, hipStream_t s) {

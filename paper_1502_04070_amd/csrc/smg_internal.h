@@ -120,6 +120,8 @@ struct StencilJob {
   const T* base_p;
   T* out_u;
   T* out_p;
+  float* out32_u;      // if set, the rows' values rounded to FP32 go here
+  float* out32_p;      // instead of out_u / out_p
   T w_u, w_p;          // weights of the velocity / pressure rows
   int diag_u, diag_p;  // 1: scale by Ahat^-1 / Shat^-1, 0: no scaling
   double* partial;     // per-tile partial sums, or NULL

@@ -97,7 +97,7 @@ __device__ __forceinline__ T res_row(FR R) {
 enum : unsigned {
   F_ROWS_U = 1u, F_ROWS_P = 2u, F_IN_U = 4u, F_IN_P = 8u, F_RHS_U = 16u, F_RHS_P = 32u,
   F_BASE_U = 64u, F_BASE_P = 128u, F_DIAG_U = 256u, F_DIAG_P = 512u, F_OUT_U = 1024u,
-  F_OUT_P = 2048u, F_PARTIAL = 4096u, F_PSUB = 8192u, F_MEAN = 16384u
+  F_OUT_P = 2048u, F_PARTIAL = 4096u, F_PSUB = 8192u, F_MEAN = 16384u, F_OUT32 = 32768u
 };
 
 template <unsigned F>
@@ -116,7 +116,7 @@ struct Flags {
 template <int CLS, unsigned F, int DOM, class T, int WX, int WY, int PX, int PY>
 __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY][WX],
                                               T (*sp)[PX], int tx, int ty, int i, int j,
-                                              double& nrm) {
+                                              double& nrm, const T* rpre) {
   using FL = Flags<F>;
   constexpr int DA = CLS & 1, DB = CLS >> 1;
   const int N = J.L.N, M = 2 * N + 1;
@@ -151,9 +151,12 @@ __device__ __forceinline__ void velocity_node(const StencilJob<T>& J, T (*su)[WY
       if (hp) y += J.L.h * (c == 0 ? btx_row<CLS, T>(P) : bty_row<CLS, T>(P));
     }
     const size_t g = (size_t)c * M * M + (size_t)b * M + a;
-    const T r = (FL::on(F_RHS_U, J.rhs_u) ? J.rhs_u[g] : T(0)) - y;
+    const T r = (rpre ? rpre[c] : FL::on(F_RHS_U, J.rhs_u) ? J.rhs_u[g] : T(0)) - y;
     if (FL::on(F_PARTIAL, J.partial) && interior) nrm += (double)r * (double)r;
-    if (FL::on(F_OUT_U, J.out_u)) {
+    if (FL::on(F_OUT32, J.out32_u)) {
+      const T v = (FL::on(F_BASE_U, J.base_u) ? J.base_u[g] : T(0)) + J.w_u * dscale * r;
+      J.out32_u[g] = interior ? (float)v : 0.0f;
+    } else if (FL::on(F_OUT_U, J.out_u)) {
       const T v = (FL::on(F_BASE_U, J.base_u) ? J.base_u[g] : T(0)) + J.w_u * dscale * r;
       J.out_u[g] = interior ? v : T(0);
     }
@@ -176,11 +179,32 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
   const int ntx = (N + TX) / TX;
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
-  const bool rows_u = (F == 0) ? (J.out_u != nullptr || J.partial != nullptr) : (F & F_ROWS_U) != 0;
-  const bool rows_p = (F == 0) ? (J.out_p != nullptr || J.partial != nullptr) : (F & F_ROWS_P) != 0;
+  const bool rows_u = (F == 0) ? (J.out_u || J.out32_u || J.partial) : (F & F_ROWS_U) != 0;
+  const bool rows_p = (F == 0) ? (J.out_p || J.out32_p || J.partial) : (F & F_ROWS_P) != 0;
   const bool hu = FL::on(F_IN_U, J.in_u);
   const bool hp = rows_u && FL::on(F_IN_P, J.in_p);
-  // the input windows, every load in flight at once
+  const int tx = tid % TX, ty = tid / TX;
+  const int i = i0 + tx, j = j0 + ty;
+  // the done flag, the input windows and (in the compile-time modes) this
+  // thread's right-hand side: every load in flight at once; the flag is
+  // tested once the windows have arrived
+  const int dn = J.done ? *J.done : 0;
+  constexpr bool PRE_U = F != 0 && (F & F_RHS_U) && (F & F_ROWS_U);
+  constexpr bool PRE_P = F != 0 && (F & F_RHS_P) && (F & F_ROWS_P);
+  T ru[4][2] = {}, rp = T(0);
+  if (i <= N && j <= N) {
+    if constexpr (PRE_U) {
+#pragma unroll
+      for (int cls = 0; cls < 4; ++cls) {
+        const int a = 2 * i + (cls & 1), b = 2 * j + (cls >> 1);
+        if (a <= 2 * N && b <= 2 * N) {
+          ru[cls][0] = J.rhs_u[(size_t)b * M + a];
+          ru[cls][1] = J.rhs_u[(size_t)M * M + (size_t)b * M + a];
+        }
+      }
+    }
+    if constexpr (PRE_P) rp = J.rhs_p[(size_t)j * NP + i];
+  }
   Staged<WX * WY, NT, 2, T> uw;
   Staged<PX * PY, NT, 2, T> pw;
   if (hu)
@@ -210,16 +234,15 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       if (FL::on(F_PSUB, J.in_p_sub)) x -= v[1];
       sp[e / PX][e % PX] = x;
     });
+  if (dn) return;   // the same value in every thread of the block
   if (hu || hp) __syncthreads();
-  const int tx = tid % TX, ty = tid / TX;
-  const int i = i0 + tx, j = j0 + ty;
   double nrm = 0.0;
   if (i <= N && j <= N) {
     if (rows_u) {
-      velocity_node<0, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<1, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<2, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
-      velocity_node<3, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm);
+      velocity_node<0, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm, PRE_U ? ru[0] : nullptr);
+      velocity_node<1, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm, PRE_U ? ru[1] : nullptr);
+      velocity_node<2, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm, PRE_U ? ru[2] : nullptr);
+      velocity_node<3, F, DOM, T, WX, WY, PX, PY>(J, su, sp, tx, ty, i, j, nrm, PRE_U ? ru[3] : nullptr);
     }
     if (rows_p) {
       const int la = 2 * tx + 2, lb = 2 * ty + 2;
@@ -236,9 +259,12 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
       const size_t g = (size_t)j * NP + i;
       // vertices outside the domain carry no pressure unknown: zero row
       const bool pin = dom_p(N, dom, i, j);
-      const T r = pin ? (FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y : T(0);
+      const T r = pin ? (PRE_P ? rp : FL::on(F_RHS_P, J.rhs_p) ? J.rhs_p[g] : T(0)) - y : T(0);
       if (FL::on(F_PARTIAL, J.partial)) nrm += (double)r * (double)r;
-      if (FL::on(F_OUT_P, J.out_p)) {
+      if (FL::on(F_OUT32, J.out32_p)) {
+        const T d = FL::on_int(F_DIAG_P, J.diag_p) ? J.L.sinv[g] : T(1);
+        J.out32_p[g] = pin ? (float)((FL::on(F_BASE_P, J.base_p) ? J.base_p[g] : T(0)) + J.w_p * d * r) : 0.0f;
+      } else if (FL::on(F_OUT_P, J.out_p)) {
         const T d = FL::on_int(F_DIAG_P, J.diag_p) ? J.L.sinv[g] : T(1);
         J.out_p[g] = pin ? (FL::on(F_BASE_P, J.base_p) ? J.base_p[g] : T(0)) + J.w_p * d * r : T(0);
       }
@@ -268,7 +294,6 @@ __device__ __forceinline__ void stencil_tile(const StencilJob<T>& J, int tile) {
 
 template <class T, int TX, int TY, unsigned F>
 __global__ __launch_bounds__(TX* TY) void k_stencil(StencilJob<T> J) {
-  if (J.done && *J.done) return;
   stencil_tile<T, TX, TY, F, -1>(J, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
@@ -291,6 +316,8 @@ constexpr unsigned M_RESID = RW_UP | F_IN_U | F_IN_P | F_RHS_U | F_RHS_P | OUT_U
 constexpr unsigned M_RESID_NORM = RW_UP | F_IN_U | F_IN_P | F_RHS_U | F_RHS_P | F_PARTIAL;
 constexpr unsigned M_RESID_NORM_MEAN = M_RESID_NORM | F_MEAN;
 constexpr unsigned M_RESID_BOTH_MEAN = M_RESID_NORM_MEAN | OUT_UP;
+constexpr unsigned M_RESID_BOTH32 = M_RESID_NORM | OUT_UP | F_OUT32;
+constexpr unsigned M_RESID_BOTH_MEAN32 = M_RESID_BOTH_MEAN | F_OUT32;
 constexpr unsigned M_RESID_BOTH = M_RESID | F_PARTIAL;
 constexpr unsigned M_NE1 = M_RESID | F_DIAG_U | F_DIAG_P;
 constexpr unsigned M_NE1Z = RW_UP | F_RHS_U | F_RHS_P | F_DIAG_U | F_DIAG_P | OUT_UP;
@@ -327,6 +354,9 @@ unsigned stencil_flags(const StencilJob<T>& J, int rows) {
   if (J.diag_p && (rows & ROWS_P)) f |= F_DIAG_P;
   if (J.out_u && (rows & ROWS_U)) f |= F_OUT_U;
   if (J.out_p && (rows & ROWS_P)) f |= F_OUT_P;
+  // FP32 outputs: a specialization only when both row kinds go to FP32
+  if (J.out32_u && J.out32_p && !J.out_u && !J.out_p && rows == ROWS_UP) f |= F_OUT_U | F_OUT_P | F_OUT32;
+  else if (J.out32_u || J.out32_p) f |= 1u << 30;   // generic kernel
   if (J.partial) f |= F_PARTIAL;
   if (J.mean_partial && J.in_p && (rows & ROWS_U)) f |= F_MEAN;
   return f;
@@ -336,7 +366,6 @@ unsigned stencil_flags(const StencilJob<T>& J, int rows) {
 // summed square by square
 template <class T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_stencil_uj(StencilJob<T> J) {
-  if (J.done && *J.done) return;
   stencil_tile<T, TX, TY, 0u, SMG_DOM_UNIONJACK>(J, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
@@ -345,8 +374,8 @@ static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s
   const int nb = ((J.L.N + TX) / TX) * ((J.L.N + TY) / TY);
   if (J.L.dom == SMG_DOM_UNIONJACK) {
     StencilJob<T> G = J;
-    if (!(rows & ROWS_U)) { G.out_u = nullptr; }
-    if (!(rows & ROWS_P)) { G.out_p = nullptr; }
+    if (!(rows & ROWS_U)) { G.out_u = nullptr; G.out32_u = nullptr; }
+    if (!(rows & ROWS_P)) { G.out_p = nullptr; G.out32_p = nullptr; }
     k_stencil_uj<T, TX, TY><<<nb, TX * TY, 0, s>>>(G);
     return;
   }
@@ -355,7 +384,7 @@ static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s
   case MODE: k_stencil<T, TX, TY, MODE><<<nb, TX * TY, 0, s>>>(J); return;
   switch (f) {
     SMG_CASE(M_APPLY) SMG_CASE(M_RESID) SMG_CASE(M_RESID_NORM) SMG_CASE(M_RESID_BOTH)
-    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
+    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN) SMG_CASE(M_RESID_BOTH32) SMG_CASE(M_RESID_BOTH_MEAN32)
     SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
     SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
     SMG_CASE(M_MASK_U) SMG_CASE(M_COPY) SMG_CASE(M_ZERO)
@@ -365,8 +394,8 @@ static void launch_stencil_shape(const StencilJob<T>& J, int rows, hipStream_t s
   // generic kernel: rows are selected by the output / partial pointers, so
   // clear the pointers of the rows that were not asked for
   StencilJob<T> G = J;
-  if (!(rows & ROWS_U)) { G.out_u = nullptr; }
-  if (!(rows & ROWS_P)) { G.out_p = nullptr; }
+  if (!(rows & ROWS_U)) { G.out_u = nullptr; G.out32_u = nullptr; }
+  if (!(rows & ROWS_P)) { G.out_p = nullptr; G.out32_p = nullptr; }
   k_stencil<T, TX, TY, 0u><<<nb, TX * TY, 0, s>>>(G);
 }
 
@@ -391,7 +420,6 @@ template <class T, int TX, int TY, unsigned F, bool PACK>
 __global__ __launch_bounds__(TX* TY) void k_stencil_b(const JobArg<StencilJob<T>> A) {
   int tile;
   const StencilJob<T> J = block_job<PACK>(A, xcd_swizzle(blockIdx.x, gridDim.x), tile);
-  if (J.done && *J.done) return;
   stencil_tile<T, TX, TY, F, -1>(J, tile);
 }
 
@@ -400,7 +428,6 @@ template <class T, int TX, int TY, bool PACK>
 __global__ __launch_bounds__(TX* TY) void k_stencil_uj_b(const JobArg<StencilJob<T>> A) {
   int tile;
   const StencilJob<T> J = block_job<PACK>(A, xcd_swizzle(blockIdx.x, gridDim.x), tile);
-  if (J.done && *J.done) return;
   stencil_tile<T, TX, TY, 0u, SMG_DOM_UNIONJACK>(J, tile);
 }
 
@@ -418,7 +445,7 @@ static void launch_stencil_b_shape(const JobArg<StencilJob<T>>& A, int nb, unsig
     return;
   switch (f) {
     SMG_CASE(M_APPLY) SMG_CASE(M_RESID) SMG_CASE(M_RESID_NORM) SMG_CASE(M_RESID_BOTH)
-    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN)
+    SMG_CASE(M_RESID_NORM_MEAN) SMG_CASE(M_RESID_BOTH_MEAN) SMG_CASE(M_RESID_BOTH32) SMG_CASE(M_RESID_BOTH_MEAN32)
     SMG_CASE(M_NE1) SMG_CASE(M_NE1Z) SMG_CASE(M_NE2) SMG_CASE(M_NE2Z)
     SMG_CASE(M_UZ1) SMG_CASE(M_UZ1Z) SMG_CASE(M_UZ2) SMG_CASE(M_UZ3) SMG_CASE(M_UZ3Z)
     SMG_CASE(M_MASK_U) SMG_CASE(M_COPY) SMG_CASE(M_ZERO)
