@@ -951,10 +951,14 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   constexpr int RW = 4 * TC + 6;       // defect: fine lattice origin (4 I0 - 4, 4 J0 - 4)
   constexpr int RPW = 2 * TC + 3;      // defect pressure: origin (2 I0 - 2, 2 J0 - 2)
   constexpr int NC1 = 2 * TC + 3;      // fine squares per side of stage 1
-  __shared__ T sx[2][XW][XW];
-  __shared__ T sxp[XPW * XPW];
-  __shared__ T sr[2][RW][RW];
-  __shared__ T srp[RPW * RPW];
+  // the defect window takes the iterate window's storage once stage 1 has
+  // read it: half the LDS, so that more workgroups fit on a CU
+  constexpr int SXN = 2 * XW * XW + XPW * XPW, SRN = 2 * RW * RW + RPW * RPW;
+  __shared__ T buf[SXN > SRN ? SXN : SRN];
+  T (*sx)[XW][XW] = reinterpret_cast<T (*)[XW][XW]>(buf);
+  T* sxp = buf + 2 * XW * XW;
+  T (*sr)[RW][RW] = reinterpret_cast<T (*)[RW][RW]>(buf);
+  T* srp = buf + 2 * RW * RW;
   const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
   const int Nc = N / 2, Mc = 2 * Nc + 1, NPc = Nc + 1;
   const int ntx = (Nc + TC) / TC;
@@ -1002,7 +1006,8 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
   xpw.put(tid, [&](int e, const T* v) { sxp[e] = v[0]; });
   __syncthreads();
   if (dn) return;   // uniform across the workgroup
-  // stage 1: fine defect on squares [2 I0 - 2, 2 I0 + 2 TC] per side
+  // stage 1: fine defect on squares [2 I0 - 2, 2 I0 + 2 TC] per side, kept
+  // in registers until every thread has read the window, then stored
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const int e = tid + it * NT;
@@ -1021,10 +1026,24 @@ __device__ __forceinline__ void rr_tile(const RRJob<T>& J, int tile) {
       const int a = 2 * i + DA, b = 2 * j + DB;
       const bool in = interior(a, b);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) sr[c][2 * cj + DB][2 * ci + DA] = in ? f1[it][2 * cls + c] - y[2 * cls + c] : T(0);
+      for (int c = 0; c < 2; ++c) f1[it][2 * cls + c] = in ? f1[it][2 * cls + c] - y[2 * cls + c] : T(0);
     }
     const bool inp = dom_p(N, DOM, i, j);
-    srp[cj * RPW + ci] = inp ? f1[it][8] - y[8] : T(0);
+    f1[it][8] = inp ? f1[it][8] - y[8] : T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int e = tid + it * NT;
+    if (e >= NC1 * NC1) break;
+    const int ci = e % NC1, cj = e / NC1;
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) sr[c][2 * cj + DB][2 * ci + DA] = f1[it][2 * cls + c];
+    }
+    srp[cj * RPW + ci] = f1[it][8];
   }
   __syncthreads();
   // stage 2: one wave per coarse node class, one lane per coarse square
