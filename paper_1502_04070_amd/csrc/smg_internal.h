@@ -162,7 +162,7 @@ int prolong_tiles(int Nc);
 template <class T>
 void launch_prolong_b(const JobArg<ProJob<T>>& A, int nb, hipStream_t s);
 
-// batched elementwise: cast d -> f (mode 0), d += f (mode 1), d = 0 (mode 2)
+// batched elementwise: d += f (mode 1), d = 0 (mode 2)
 struct EwJob {
   double* d;
   float* f;
@@ -242,7 +242,6 @@ void launch_init_state(const double* rpartials, int np, const double* fdots, Sol
 // elementwise helpers
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
-void launch_cast_f64_f32(const double* a, float* b, int64_t n, const int* done, hipStream_t s);
 // x += (double) d ; both with n entries
 void launch_axpy_f32(double* x, const float* d, int64_t n, const int* done, hipStream_t s);
 

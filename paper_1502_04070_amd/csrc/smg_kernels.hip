@@ -1272,16 +1272,6 @@ void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
   if (n > 0) k_fill<float><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
 }
 
-__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ a, float* b, int64_t n,
-                                              const int* done) {
-  if (done && *done) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < n) b[e] = (float)a[e];
-}
-void launch_cast_f64_f32(const double* a, float* b, int64_t n, const int* done, hipStream_t s) {
-  k_cast<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, b, n, done);
-}
-
 __global__ __launch_bounds__(256) void k_axpy_f32(double* x, const float* __restrict__ d, int64_t n,
                                                   const int* done) {
   if (done && *done) return;
@@ -1303,8 +1293,7 @@ __global__ __launch_bounds__(256) void k_ew_b(const JobArg<EwJob> A, int mode) {
   for (int k = 0; k < 4; ++k) {
     const int64_t e = base + k * 256 + threadIdx.x;
     if (e >= J.n) break;
-    if (mode == 0) J.f[e] = (float)J.d[e];
-    else if (mode == 1) J.d[e] += (double)J.f[e];
+    if (mode == 1) J.d[e] += (double)J.f[e];
     else J.d[e] = 0.0;
   }
 }
