@@ -770,7 +770,15 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int N0, int dom, int nc, c
   __syncthreads();
   for (int row = threadIdx.x; row < nc; row += blockDim.x) {
     double z = 0.0;
-    for (int j = 0; j < nc; ++j) z += cinv[(size_t)j * nc + row] * sr[j];
+    // eight columns' loads in flight at a time, added in column order
+    for (int j0 = 0; j0 < nc; j0 += 8) {
+      double cv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cv[u] = j0 + u < nc ? cinv[(size_t)(j0 + u) * nc + row] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < nc) z += cv[u] * sr[j0 + u];
+    }
     sz[row] = z;
   }
   __syncthreads();
