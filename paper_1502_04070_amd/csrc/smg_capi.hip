@@ -329,9 +329,14 @@ void uzawa_fused(Level& L, Vec<T> cur, Vec<T> f, Vec<T> alt, bool zg, const int*
 // With acc_u / acc_p (FP32 cycles on the finest level), a last smoothing
 // step that is a single fused NE launch adds its result to those FP64
 // vectors instead of writing it; the return value then has null pointers.
+// With rpart / mpart (FP64 cycles on the finest level), a last smoothing step
+// that is a single NE launch on 16 x 8 tiles also forms the residual of its
+// result: ||r||^2 per tile into rpart and the pressure mean pieces into
+// mpart (k_ne_res); *resd is set then.
 template <class T>
 Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s,
-                   double* acc_u = nullptr, double* acc_p = nullptr) {
+                   double* acc_u = nullptr, double* acc_p = nullptr, double* rpart = nullptr,
+                   double* mpart = nullptr, bool* resd = nullptr) {
   if (l <= H->Lc) {
     coarse_cycle<T>(H, x, f, zg, done, s);
     return x;
@@ -437,7 +442,18 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
         J.acc_u = acc_u; J.acc_p = acc_p;
         accd = true;
       }
-      if (two) launch_ne2<T>(J, false, false, s);
+      bool fused_res = false;
+      if constexpr (std::is_same<T, double>::value) {
+        if (rpart && !two && k + 1 == post && tx == 16 && ne_res_tiles(L.N) <= NE_RES_MAX_TILES) {
+          J.partial = rpart;
+          J.mean_partial = mpart;
+          launch_ne_res(J, s);
+          fused_res = true;
+          if (resd) *resd = true;
+        }
+      }
+      if (fused_res) {
+      } else if (two) launch_ne2<T>(J, false, false, s);
       else launch_ne<T>(J, false, false, tx, s);
       std::swap(cur, alt);
       k += two ? 2 : 1;
@@ -451,20 +467,28 @@ Vec<T> cycle_fused(smg_hier* H, int l, Vec<T> x, Vec<T> f, bool zg, const int* d
   return cur;
 }
 
-// iterate on the finest level with the result in x; with acc_u / acc_p the
-// result may instead have been added to those vectors (returns true then)
+// iterate on the finest level with the result in x.  Returns TOP_ACC when
+// the result was added to acc_u / acc_p instead, TOP_RES when the last
+// launch also wrote the residual partials to rpart / mpart.
+enum { TOP_ACC = 1, TOP_RES = 2 };
 template <class T>
-bool top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s,
-               double* acc_u = nullptr, double* acc_p = nullptr) {
+int top_cycle(smg_hier* H, Vec<T> x, Vec<T> f, bool zg, const int* done, hipStream_t s,
+              double* acc_u = nullptr, double* acc_p = nullptr, double* rpart = nullptr,
+              double* mpart = nullptr) {
   if (!H->fused) {
     if (zg) fill_vec<T>(H->lv[H->L], x, s);
     cycle_rec<T>(H, H->L, x, f, false, done, s);
-    return false;
+    return 0;
   }
-  Vec<T> r = cycle_fused<T>(H, H->L, x, f, zg, done, s, acc_u, acc_p);
-  if (!r.u) return true;
-  if (r.u != x.u) copy_vec<T>(H->lv[H->L], x, r, done, s);
-  return false;
+  bool resd = false;
+  Vec<T> r = cycle_fused<T>(H, H->L, x, f, zg, done, s, acc_u, acc_p, rpart, mpart, &resd);
+  if (!r.u) return TOP_ACC;
+  if (r.u != x.u) {
+    // the partials were formed for the other buffer's values, which are the
+    // same numbers: the copy does not change them
+    copy_vec<T>(H->lv[H->L], x, r, done, s);
+  }
+  return resd ? TOP_RES : 0;
 }
 
 void project_mean(smg_hier* H, int l, double* p, const int* done, hipStream_t s) {
@@ -505,8 +529,11 @@ void finish_iter(smg_hier* H, float* r32u, float* r32p, const int* done, hipStre
 void enqueue_iter64(smg_hier* H, hipStream_t s) {
   Level& T = H->lv[H->L];
   const int* done = &H->st->done;
-  top_cycle<double>(H, T.x, T.f, false, done, s);
-  finish_iter(H, nullptr, nullptr, done, s);
+  // the last smoothing step forms the residual pieces where it can (k_ne_res)
+  if (top_cycle<double>(H, T.x, T.f, false, done, s, nullptr, nullptr, T.partial, H->mpart) & TOP_RES)
+    launch_project_check(H->mpart, T.partial, ne_res_tiles(T.N), T.N, H->dom, T.x.p, H->st, H->hist, s);
+  else
+    finish_iter(H, nullptr, nullptr, done, s);
 }
 
 // one refinement step: d = cycle_fp32(r), x += d, r = F - calA x, project, test
@@ -516,7 +543,7 @@ void enqueue_iter64(smg_hier* H, hipStream_t s) {
 void enqueue_iter_mixed(smg_hier* H, hipStream_t s) {
   Level& T = H->lv[H->L];
   const int* done = &H->st->done;
-  if (!top_cycle<float>(H, T.x32, T.f32, true, done, s, T.x.u, T.x.p))
+  if (!(top_cycle<float>(H, T.x32, T.f32, true, done, s, T.x.u, T.x.p) & TOP_ACC))
     launch_axpy_f32(T.x.u, T.x32.u, T.n_u + T.n_p, done, s);
   finish_iter(H, T.f32.u, T.f32.p, done, s);
 }

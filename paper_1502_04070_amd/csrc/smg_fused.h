@@ -21,6 +21,7 @@ struct NEJob {
   const int* done;
   double* acc_u;      // FP32 steps only: if set, the new iterate is added to
   double* acc_p;      // these FP64 vectors instead of being written to ou / op
+  double* mean_partial;  // k_ne_res only: per tile (sum w_i p_i, sum w_i) of the new p
 };
 TileShape ne_tile_shape(int N);
 
@@ -53,6 +54,18 @@ void launch_ne2_b(const JobArg<NEJob<T>>& A, int nb, bool zero_guess, bool prolo
 int ne_tiles(int N);
 template <class T>
 void launch_ne(const NEJob<T>& J, bool zero_guess, bool prolong, int tile_x, hipStream_t s);
+// one NE step from a non-zero iterate on 16 x 8 tiles, then the residual of
+// the result: per tile its ||F - A x_new||^2 (partial) and the pressure mean
+// pieces of x_new (mean_partial), as the residual pass of the solve loop
+// writes them; tiles as ne_tiles with 16 x 8 tiles
+void launch_ne_res(const NEJob<double>& J, hipStream_t s);
+inline int ne_res_tiles(int N) { return ((N + 16) / 16) * ((N + 8) / 8); }
+// used only for launches of at most this many tiles (about one round of
+// workgroups): there the separate residual pass is a launch's latency, while
+// on larger grids the fused kernel's extra halo work costs more than the
+// pass (64 x 4 batch: 624 us against 344 + 191 us)
+constexpr int NE_RES_MAX_TILES = 1024;
+void launch_ne_res_b(const JobArg<NEJob<double>>& A, int nb, int dom, hipStream_t s);
 
 // fused defect and restriction: (cu, cp) = P^T (F - A x), L = fine level
 template <class T>

@@ -504,6 +504,230 @@ void launch_ne(const NEJob<T>& J, bool zg, bool pro, int tx, hipStream_t s) {
 template void launch_ne<double>(const NEJob<double>&, bool, bool, int, hipStream_t);
 template void launch_ne<float>(const NEJob<float>&, bool, bool, int, hipStream_t);
 
+
+// ---------------------------------------------------------------------------
+// k_ne_res: the last smoothing step on the finest level together with the
+// residual pass of the solve loop.  Stage 0 loads x on the tile + 3 squares;
+// stage 1 writes y = L^-1 (F - A x) on the tile + 2; stage 2 forms
+// x_new = x + tau L^-1 A y on the tile + 1 (one thread per square, all nine
+// rows, the same expressions as k_ne) and writes it over x in LDS (each
+// thread reads and writes only its own square's points there) and, on the
+// tile, to memory; stage 3 forms F - A x_new on the tile for ||r||^2 and the
+// pressure mean pieces of x_new.  16 x 8 tiles, 256 threads.
+// ---------------------------------------------------------------------------
+
+template <class T, int DOM>
+__device__ __forceinline__ void ne_res_tile(const NEJob<T>& J, int tile) {
+  constexpr int TX = 16, TY = 8, NT = 2 * TX * TY;
+  using XWn = XWindow<T, TX, TY, 3, NT, DOM>;
+  constexpr int XW = XWn::XW, XH = XWn::XH;       // x: lattice origin (2 i0 - 6, 2 j0 - 6)
+  constexpr int XPW = XWn::XPW, XPH = XWn::XPH;   // x pressure: origin (i0 - 3, j0 - 3)
+  constexpr int YW = 2 * TX + 8, YH = 2 * TY + 8; // y: lattice origin (2 i0 - 4, 2 j0 - 4)
+  constexpr int YPW = TX + 4, YPH = TY + 4;       // y pressure: origin (i0 - 2, j0 - 2)
+  constexpr int C1W = TX + 4, C1H = TY + 4;       // stage-1 squares (tile + 2)
+  constexpr int C2W = TX + 2, C2H = TY + 2;       // stage-2 squares (tile + 1)
+  static_assert(C1W * C1H <= NT && C2W * C2H <= NT, "one stage-1 and one stage-2 square per thread");
+  __shared__ T sx[2][XH][XW];
+  __shared__ T sxp[XPH * XPW];
+  __shared__ T sy[2][YH][YW];
+  __shared__ T syp[YPH * YPW];
+  __shared__ double red[NT / 64];
+  const int N = J.L.N, M = 2 * N + 1, NP = N + 1;
+  const int ntx = (N + TX) / TX;
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  const T tau = J.tau;
+  auto interior = [&](int a, int b) { return dom_u(N, DOM, a, b); };
+
+  // every global input requested before the first wait: the done flag,
+  // the stage-1 right-hand side and Shat^-1, the stage-2 Shat^-1, the
+  // stage-3 right-hand side (two threads per owned square: classes 0, 1 /
+  // classes 2, 3 and the pressure row), then the iterate window
+  const int dn = J.done ? *J.done : 0;
+  const int c1i = tid % C1W, c1j = tid / C1W;
+  const int i1 = i0 - 2 + c1i, j1 = j0 - 2 + c1j;
+  const bool act1 = tid < C1W * C1H;
+  T f1[9], s1 = T(0);
+#pragma unroll
+  for (int cls = 0; cls < 4; ++cls) {
+    const int a = 2 * i1 + (cls & 1), b = 2 * j1 + (cls >> 1);
+    const bool in = act1 && interior(a, b);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f1[2 * cls + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+  }
+  const bool inp1 = act1 && dom_p(N, DOM, i1, j1);
+  f1[8] = inp1 ? J.fp[(size_t)j1 * NP + i1] : T(0);
+  if (inp1) s1 = J.L.sinv[(size_t)j1 * NP + i1];
+  const int c2i = tid % C2W, c2j = tid / C2W;
+  const int i2 = i0 - 1 + c2i, j2 = j0 - 1 + c2j;
+  const bool act2 = tid < C2W * C2H && i2 >= 0 && j2 >= 0 && i2 <= N && j2 <= N;
+  T s2 = T(0);
+  if (act2) s2 = J.L.sinv[(size_t)j2 * NP + i2];
+  const int part = tid / (TX * TY), q3 = tid % (TX * TY);
+  const int t3x = q3 % TX, t3y = q3 / TX;
+  const int i3 = i0 + t3x, j3 = j0 + t3y;
+  const bool own3 = i3 <= N && j3 <= N;
+  T f3[5];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int cls = 2 * part + k, a = 2 * i3 + (cls & 1), b = 2 * j3 + (cls >> 1);
+    const bool in = own3 && a <= 2 * N && b <= 2 * N && interior(a, b);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f3[2 * k + c] = in ? J.fu[(size_t)c * M * M + (size_t)b * M + a] : T(0);
+  }
+  f3[4] = (part == 1 && own3 && dom_p(N, DOM, i3, j3)) ? J.fp[(size_t)j3 * NP + i3] : T(0);
+  {
+    XWn w;
+    w.fetch(J, i0, j0, tid);
+    w.put(tid, sx, sxp);
+  }
+  __syncthreads();
+  if (dn) return;   // uniform across the workgroup
+
+  // ---- stage 1: y = L^-1 (F - A x) on the tile + 2
+  if (act1) {
+    T y[9], ad[4];
+    auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * c1j + 2 + db][2 * c1i + 2 + da]; };
+    auto PA = [&](int di, int dj) -> T { return sxp[(c1j + 1 + dj) * XPW + (c1i + 1 + di)]; };
+    sq_rows<T, true, true, DOM>(J.L, i1, j1, UA, PA, y, ad);
+#pragma unroll
+    for (int cls = 0; cls < 4; ++cls) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i1 + DA, b = 2 * j1 + DB;
+      const bool in = interior(a, b);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T r = T(0);
+        if (in) r = f1[2 * cls + c] - y[2 * cls + c];
+        sy[c][2 * c1j + DB][2 * c1i + DA] = in ? ad[cls] * r : T(0);
+      }
+    }
+    T rp = T(0);
+    if (inp1) rp = f1[8] - y[8];
+    syp[c1j * YPW + c1i] = inp1 ? s1 * rp : T(0);
+  }
+  __syncthreads();
+
+  // ---- stage 2: x_new = x + tau L^-1 A y on the tile + 1, over x in LDS
+  if (act2) {
+    auto UA = [&](int c, int da, int db) -> T { return sy[c][2 * c2j + 2 + db][2 * c2i + 2 + da]; };
+    auto PA = [&](int di, int dj) -> T { return syp[(c2j + 1 + dj) * YPW + (c2i + 1 + di)]; };
+    const bool mine = c2i >= 1 && c2i <= TX && c2j >= 1 && c2j <= TY;
+    auto emit = [&](int cls, T z0, T z1, T ad) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i2 + DA, b = 2 * j2 + DB;
+      if (a > 2 * N || b > 2 * N) return;
+      const bool in = interior(a, b);
+      T& x0 = sx[0][2 * c2j + 4 + DB][2 * c2i + 4 + DA];
+      T& x1 = sx[1][2 * c2j + 4 + DB][2 * c2i + 4 + DA];
+      const T d = ad * tau;
+      const T v0 = in ? x0 + d * z0 : T(0);
+      const T v1 = in ? x1 + d * z1 : T(0);
+      x0 = v0;
+      x1 = v1;
+      if (mine) {
+        const size_t g = (size_t)b * M + a;
+        J.ou[g] = v0;
+        J.ou[(size_t)M * M + g] = v1;
+      }
+    };
+    T z0, z1, ad;
+    sq_vel<0, T, true, true, DOM>(J.L, i2, j2, UA, PA, z0, z1, ad);
+    emit(0, z0, z1, ad);
+    sq_vel<1, T, true, true, DOM>(J.L, i2, j2, UA, PA, z0, z1, ad);
+    emit(1, z0, z1, ad);
+    sq_vel<2, T, true, true, DOM>(J.L, i2, j2, UA, PA, z0, z1, ad);
+    emit(2, z0, z1, ad);
+    sq_vel<3, T, true, true, DOM>(J.L, i2, j2, UA, PA, z0, z1, ad);
+    emit(3, z0, z1, ad);
+    const T zp = sq_prow<T, DOM>(J.L, i2, j2, UA);
+    T& xo = sxp[(c2j + 2) * XPW + c2i + 2];
+    const T vp = xo + tau * s2 * zp;
+    xo = vp;
+    if (mine) J.op[(size_t)j2 * NP + i2] = vp;
+  }
+  __syncthreads();
+
+  // ---- stage 3: F - A x_new on the tile (two threads per square), the
+  // residual norm over the owned rows and the pressure mean pieces of x_new
+  double nrm = 0.0, wp = 0.0, w = 0.0;
+  if (own3) {
+    auto UA = [&](int c, int da, int db) -> T { return sx[c][2 * t3y + 6 + db][2 * t3x + 6 + da]; };
+    auto PA = [&](int di, int dj) -> T { return sxp[(t3y + 3 + dj) * XPW + (t3x + 3 + di)]; };
+    auto res = [&](int k, int cls, T z0, T z1) {
+      const int DA = cls & 1, DB = cls >> 1;
+      const int a = 2 * i3 + DA, b = 2 * j3 + DB;
+      if (a > 2 * N || b > 2 * N || !interior(a, b)) return;
+      const T r0 = f3[2 * k] - z0, r1 = f3[2 * k + 1] - z1;
+      nrm += (double)r0 * (double)r0;
+      nrm += (double)r1 * (double)r1;
+    };
+    T z0, z1, ad;
+    if (part == 0) {
+      sq_vel<0, T, true, true, DOM>(J.L, i3, j3, UA, PA, z0, z1, ad);
+      res(0, 0, z0, z1);
+      sq_vel<1, T, true, true, DOM>(J.L, i3, j3, UA, PA, z0, z1, ad);
+      res(1, 1, z0, z1);
+    } else {
+      sq_vel<2, T, true, true, DOM>(J.L, i3, j3, UA, PA, z0, z1, ad);
+      res(0, 2, z0, z1);
+      sq_vel<3, T, true, true, DOM>(J.L, i3, j3, UA, PA, z0, z1, ad);
+      res(1, 3, z0, z1);
+      if (dom_p(N, DOM, i3, j3)) {
+        const T rp = f3[4] - sq_prow<T, DOM>(J.L, i3, j3, UA);
+        nrm += (double)rp * (double)rp;
+      }
+      w = p1_count_w(N, DOM, i3, j3);
+      wp = w * (double)sxp[(t3y + 3) * XPW + t3x + 3];
+    }
+  }
+  if (J.partial) {
+    const double s = wg_sum<NT>(nrm, red);
+    if (tid == 0) J.partial[tile] = s;
+  }
+  if (J.mean_partial) {
+    __syncthreads();
+    const double sw = wg_sum<NT>(wp, red);
+    __syncthreads();
+    const double s0 = wg_sum<NT>(w, red);
+    if (tid == 0) {
+      J.mean_partial[2 * tile] = sw;
+      J.mean_partial[2 * tile + 1] = s0;
+    }
+  }
+}
+
+template <int DOM>
+__global__ __launch_bounds__(256) void k_ne_res(NEJob<double> J) {
+  ne_res_tile<double, DOM>(J, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <bool PACK, int DOM>
+__global__ __launch_bounds__(256) void k_ne_res_b(const JobArg<NEJob<double>> A) {
+  int tile;
+  const NEJob<double> J = block_job<PACK>(A, xcd_remap(blockIdx.x, gridDim.x), tile);
+  ne_res_tile<double, DOM>(J, tile);
+}
+
+void launch_ne_res(const NEJob<double>& J, hipStream_t s) {
+  const int nb = ((J.L.N + 16) / 16) * ((J.L.N + 8) / 8);
+  if (J.L.dom == SMG_DOM_LSHAPE) k_ne_res<SMG_DOM_LSHAPE><<<nb, 256, 0, s>>>(J);
+  else if (J.L.dom == SMG_DOM_UNIONJACK) k_ne_res<SMG_DOM_UNIONJACK><<<nb, 256, 0, s>>>(J);
+  else k_ne_res<SMG_DOM_SQUARE><<<nb, 256, 0, s>>>(J);
+}
+
+template <int DOM>
+static void launch_ne_res_b_dom(const JobArg<NEJob<double>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_ne_res_b<true, DOM><<<nb, 256, 0, s>>>(A);
+  else k_ne_res_b<false, DOM><<<nb, 256, 0, s>>>(A);
+}
+
+void launch_ne_res_b(const JobArg<NEJob<double>>& A, int nb, int dom, hipStream_t s) {
+  if (dom == SMG_DOM_LSHAPE) launch_ne_res_b_dom<SMG_DOM_LSHAPE>(A, nb, s);
+  else if (dom == SMG_DOM_UNIONJACK) launch_ne_res_b_dom<SMG_DOM_UNIONJACK>(A, nb, s);
+  else launch_ne_res_b_dom<SMG_DOM_SQUARE>(A, nb, s);
+}
+
 // ---------------------------------------------------------------------------
 // k_ne2: two fused normal-equation steps on a TX x TY tile of squares
 // ---------------------------------------------------------------------------
