@@ -80,12 +80,24 @@ def roofline_block(kernel, Ns, avg_ms, traffic=None):
             "kernel_min_frac": own / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def _code_only(text, name):
+    """The source without its comments and with whitespace collapsed, so that
+    an edit of a comment keeps the hash of the code the counters measured."""
+    import re
+    if name.endswith(".py"):
+        return text
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def ne_kernel_source_hash():
+    """SHA-256 over the code (comments removed) of the NE kernel's sources."""
     import hashlib
     hsh = hashlib.sha256()
     for name in NE_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1502_04070_amd", "csrc", name), "rb") as fh:
-            hsh.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1502_04070_amd", "csrc", name), encoding="utf-8") as fh:
+            hsh.update(_code_only(fh.read(), name).encode())
     return hsh.hexdigest()
 
 

@@ -243,6 +243,8 @@ int smg_solve_error(smg_t h, const double* fu, const double* gp, const double* u
  * (u, p) are the initial guess on entry and the solution on return (mean-free
  * pressure).  iters, relres and history (maxit doubles, relative residual
  * after each iterate) may be NULL; they are HOST pointers.  Synchronous.
+ * rtol = 0 runs exactly maxit iterates (ending with SMG_NOCONV unless the
+ * residual is exactly zero); the host then checks the state only at the end.
  * Returns SMG_OK, SMG_NOCONV, SMG_DIVERGED, SMG_ENONFINITE or SMG_EINCOMPAT (soft) or a
  * hard error.
  */

@@ -9,13 +9,19 @@
 //   k_ne2           two normal-equation steps in one launch on levels with
 //                   8 x 8 tiles: every intermediate lives in LDS on the tile
 //                   plus a halo that shrinks by one square per operator.
+//   k_ne2rr         from a zero iterate, two normal-equation steps, the defect
+//                   and its restriction in one launch (levels with 8 x 8 tiles).
+//   k_ne_res        the last smoothing step of an FP64 iterate on the finest
+//                   level together with the solve loop's residual pass (the
+//                   residual norm and pressure mean pieces of the new iterate).
 //   k_resid_restrict  the defect F - A x and its restriction P^T (F - A x)
 //                   (Section 3) in one launch; the fine defect lives only in LDS.
 //   k_coarse_cycle  the whole iterate on the coarse levels (N <= 8 by default)
 //                   by one workgroup with every vector of those levels in LDS,
 //                   including the exact solve on level 0.
-//   k_project_partials  the pressure mean projection from partial sums that
-//                   the residual-norm pass of the solve loop produces.
+//   k_project_partials, k_project_check  the pressure mean projection from
+//                   the partial sums of the residual pass, and the
+//                   convergence test by the last workgroup.
 //
 // Bandwidth: an unfused normal-equation step streams x, F and the
 // intermediate twice (6 vectors); k_ne streams x and F once and writes x once
