@@ -11,6 +11,8 @@
 * rtol = 0 runs exactly maxit iterates (the loop launches them without
   host checks), ends with status noconv and reports the same history as a
   tolerance no solve reaches.
+* The last smoothing step with the residual pass fused into it gives the
+  same iterates and residual history as the separate pass.
 """
 import numpy as np
 import pytest
@@ -84,3 +86,23 @@ def test_rtol_zero_runs_maxit_iterates():
     loads = [_load(hh, sd) for hh, sd in zip(B.instances, (5, 6))]
     us, ps, infos = B.solve([a for a, _ in loads], [b for _, b in loads], rtol=0.0, maxit=7)
     assert [i.iters for i in infos] == [7, 7] and all(i.status == "noconv" for i in infos)
+
+
+@pytest.mark.parametrize("domain", ["square", "l_shape"])
+def test_fused_last_step_residual_matches_separate_pass(domain):
+    """16 x 8 tiles: the last smoothing step also forms the residual pieces
+    (k_ne_res); 8 x 8 tiles with one step per launch: a separate residual
+    pass does.  Same iterates, same residual history to rounding."""
+    N, beta = 128, 10.0
+    print(f"fused residual N={N} domain={domain}", flush=True)
+    ha = Hierarchy(N, beta, domain=domain, schedule={"tile_x": 16, "fuse_depth": 1})
+    hb = Hierarchy(N, beta, domain=domain, schedule={"tile_x": 8, "fuse_depth": 1})
+    fu, gp = _load(ha, 11)
+    Ua, Pa, ia = ha.solve(fu, gp, rtol=1e-10, maxit=300)
+    Ub, Pb, ib = hb.solve(fu, gp, rtol=1e-10, maxit=300)
+    assert ia.status == ib.status == "ok"
+    assert ia.iters == ib.iters, (ia.iters, ib.iters)
+    # equal to rounding of the residual itself (about 1e-15 of ||F||), which
+    # dominates the last, smallest entries
+    assert np.allclose(ia.history, ib.history, rtol=1e-9, atol=1e-14)
+    assert _rel(Ua, Ub) <= 1e-12 and _rel(Pa, Pb) <= 1e-12, (_rel(Ua, Ub), _rel(Pa, Pb))
