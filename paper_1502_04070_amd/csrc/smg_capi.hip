@@ -816,8 +816,9 @@ int smg_setup(int N, double beta, const smg_params* prm_in, smg_t* out) {
     for (int l = 0; l <= L && l <= CC_MAX_LEVELS; ++l) {
       if ((prm.n0 << l) > cmax) break;
       const size_t need = coarse_cycle_lds(prm.n0, l, sizeof(double));
-      // the job staged in static LDS comes on top of the dynamic part
-      if (need + sizeof(CoarseJob<double>) > limit) break;
+      // the job, the op list and level 0's inverse staged in static LDS come
+      // on top of the dynamic part
+      if (need + sizeof(CoarseJob<double>) + CC_STATIC_LDS > limit) break;
       if (need > 65536 && (coarse_cycle_allow_lds<double>(need) != 0 ||
                            coarse_cycle_allow_lds<float>(coarse_cycle_lds(prm.n0, l, sizeof(float))) != 0)) {
         (void)hipGetLastError();

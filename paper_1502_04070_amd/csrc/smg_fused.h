@@ -109,6 +109,10 @@ constexpr int CC_MAX_LEVELS = 5;
 enum { CC_NE = 1, CC_UZAWA = 2, CC_RESTRICT = 3, CC_PROLONG = 4, CC_COARSE = 5 };
 inline int cc_op(int kind, int level, int zg) { return kind | (level << 8) | (zg << 16); }
 constexpr int CC_MAX_OPS = 256;
+// level 0's inverse is staged in LDS up to this order (the 27 unknowns of
+// n0 = 2 fit); the static LDS of the kernel on top of its level storage
+constexpr int CC_CINV_MAX = 32;
+constexpr size_t CC_STATIC_LDS = CC_MAX_OPS * sizeof(int) + CC_CINV_MAX * CC_CINV_MAX * sizeof(double);
 
 template <class T>
 struct CoarseJob {

@@ -1626,16 +1626,15 @@ template void launch_ne2rr_b<double>(const JobArg<NERRJob<double>>&, int, int, h
 template void launch_ne2rr_b<float>(const JobArg<NERRJob<float>>&, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
+constexpr int CC_THREADS = 768;
 #include "smg_coarse.inc"
 
 // 12 waves: the nine item types of a phase on the levels up to N = 8 fit in
 // one pass, and the register budget (three waves per SIMD) still holds the
 // FP64 stencil rows without spills
-constexpr int CC_THREADS = 768;
 
 template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle(CoarseJob<T> J) {
-  if (J.done && *J.done) return;
   coarse_body<T, DOM>(J);
 }
 
@@ -1651,7 +1650,6 @@ __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle_b(const CoarseJob<T
     for (int e = threadIdx.x; e < (int)(sizeof(CoarseJob<T>) / 4); e += blockDim.x) dst[e] = src[e];
   }
   __syncthreads();
-  if (sj.done && *sj.done) return;
   coarse_body<T, DOM>(sj);
 }
 
