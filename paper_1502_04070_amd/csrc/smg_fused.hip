@@ -1629,9 +1629,9 @@ template void launch_ne2rr_b<float>(const JobArg<NERRJob<float>>&, int, int, hip
 constexpr int CC_THREADS = 768;
 #include "smg_coarse.inc"
 
-// 12 waves: the nine item types of a phase on the levels up to N = 8 fit in
-// one pass, and the register budget (three waves per SIMD) still holds the
-// FP64 stencil rows without spills
+// 12 waves: the five item types of a phase (four node classes, the pressure)
+// on the levels up to N = 8 fit in one pass, and the register budget (three
+// waves per SIMD) still holds the FP64 stencil rows without spills
 
 template <class T, int DOM>
 __global__ __launch_bounds__(CC_THREADS) void k_coarse_cycle(CoarseJob<T> J) {
