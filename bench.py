@@ -117,7 +117,7 @@ def counter_traffic(path=COUNTER_SUMMARY):
         return None
 
 
-def cpu_baseline(n_cycles=30):
+def cpu_baseline(n_cycles=120):
     """The oracle (SciPy CSR, FP64) on a bounded sample of the same workload:
     `n_cycles` V(2,2) iterates plus residual norms for each beta at h = 1/128."""
     try:
