@@ -17,6 +17,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <initializer_list>
 #include <type_traits>
 #include <vector>
 
@@ -45,6 +46,10 @@ using host::fail;
     hipError_t e_ = (x);                                                               \
     if (e_ != hipSuccess) return fail(SMG_EHIP, "%s: %s", #x, hipGetErrorString(e_));  \
   } while (0)
+
+// iterates per repeated-iterate graph of a solve (the iterate graph launched
+// alone covers the rest of a chunk)
+constexpr int ITER_GRAPH_REPS = 4;
 
 template <class T>
 struct Vec {
@@ -97,7 +102,8 @@ struct smg_hier {
   double* fdots = nullptr;         // 2 doubles
   double* enorm = nullptr;         // 4 doubles (error-measure pieces)
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t g64 = nullptr, g32 = nullptr;
+  hipGraphExec_t g64 = nullptr, g32 = nullptr;     // one iterate
+  hipGraphExec_t g64r = nullptr, g32r = nullptr;   // ITER_GRAPH_REPS iterates
   hipGraphExec_t gerr = nullptr;   // protocol iterate (cycle, projection, error measure)
   const void* gerr_key[6] = {};    // the vectors it was captured with
   // bumped whenever a value that captured launches carry changes (damping,
@@ -124,9 +130,8 @@ struct smg_hier {
   }
   ~smg_hier() {
     // teardown: errors cannot be reported from a destructor
-    if (g64) (void)hipGraphExecDestroy(g64);
-    if (g32) (void)hipGraphExecDestroy(g32);
-    if (gerr) (void)hipGraphExecDestroy(gerr);
+    for (hipGraphExec_t g : {g64, g32, g64r, g32r, gerr})
+      if (g) (void)hipGraphExecDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -551,10 +556,10 @@ void enqueue_iter_mixed(smg_hier* H, hipStream_t s) {
 // forget the captured iterates of one hierarchy (their launches carry values
 // that changed)
 void drop_solve_graphs(smg_hier* H) {
-  if (H->g64) (void)hipGraphExecDestroy(H->g64);
-  if (H->g32) (void)hipGraphExecDestroy(H->g32);
-  if (H->gerr) (void)hipGraphExecDestroy(H->gerr);
-  H->g64 = H->g32 = H->gerr = nullptr;
+  for (hipGraphExec_t* g : {&H->g64, &H->g32, &H->g64r, &H->g32r, &H->gerr}) {
+    if (*g) (void)hipGraphExecDestroy(*g);
+    *g = nullptr;
+  }
   ++H->gen;
 }
 
@@ -570,10 +575,11 @@ int reserve_history(smg_hier* H, int maxit) {
   return SMG_OK;
 }
 
-int capture(smg_hier* H, void (*fn)(smg_hier*, hipStream_t), hipGraphExec_t* out) {
+// `reps` iterates enqueued by fn, captured as one graph
+int capture(smg_hier* H, void (*fn)(smg_hier*, hipStream_t), hipGraphExec_t* out, int reps = 1) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
-  fn(H, H->cap_stream);
+  for (int r = 0; r < reps; ++r) fn(H, H->cap_stream);
   HIPCHK(hipStreamEndCapture(H->cap_stream, &g));
   hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -594,6 +600,23 @@ int launch_status(const char* what) {
   return SMG_OK;
 }
 
+// c iterates: graphs of ITER_GRAPH_REPS iterates while they fit, then graphs
+// of one (rep may be null).  Kernels within a graph follow each other without
+// a gap; each graph launch starts after a bubble of several microseconds.
+hipError_t launch_iters(hipGraphExec_t one, hipGraphExec_t rep, int c, hipStream_t s) {
+  int q = 0;
+  if (rep)
+    for (; q + ITER_GRAPH_REPS <= c; q += ITER_GRAPH_REPS) {
+      const hipError_t e = hipGraphLaunch(rep, s);
+      if (e != hipSuccess) return e;
+    }
+  for (; q < c; ++q) {
+    const hipError_t e = hipGraphLaunch(one, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // the solve loop shared by the FP64 and the mixed-precision variants
 int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, double rtol, int maxit,
               double* u, double* p, int* iters, double* relres, double* history, hipStream_t s) {
@@ -606,8 +629,13 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
     if (rc) return rc;
   }
   hipGraphExec_t* gexec = mixed ? &H->g32 : &H->g64;
+  hipGraphExec_t* grep = mixed ? &H->g32r : &H->g64r;
   if (!*gexec) {
     int rc = capture(H, mixed ? enqueue_iter_mixed : enqueue_iter64, gexec);
+    if (rc) return rc;
+  }
+  if (!*grep) {
+    int rc = capture(H, mixed ? enqueue_iter_mixed : enqueue_iter64, grep, ITER_GRAPH_REPS);
     if (rc) return rc;
   }
   const size_t bu = sizeof(double) * T.n_u, bp = sizeof(double) * T.n_p;
@@ -646,7 +674,7 @@ int run_solve(smg_hier* H, bool mixed, const double* fu, const double* gp, doubl
   int launched = 0, chunk = 2;
   while (!H->st_host->done && launched < maxit) {
     const int k = std::min(chunk, maxit - launched);
-    for (int q = 0; q < k; ++q) HIPCHK(hipGraphLaunch(*gexec, s));
+    HIPCHK(launch_iters(*gexec, *grep, k, s));
     launched += k;
     HIPCHK(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
