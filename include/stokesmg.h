@@ -324,8 +324,9 @@ int smg_dot(smg_t h, int level, int which, const double* a, const double* b, dou
  * of every instance is computed exactly as by the single-instance solver;
  * one launch serves every instance taking part in a stage (instances are
  * aligned by depth below their own finest level), and the whole iterate of
- * the batch is replayed from one captured HIP graph.  Converged instances are
- * skipped by their own convergence flag.  Several right-hand sides of one
+ * the batch is replayed from captured HIP graphs (one of one iterate, one of
+ * four, launched so that a chunk runs exactly its iterates).  Converged
+ * instances are skipped by their own convergence flag.  Several right-hand sides of one
  * problem are several instances with the same N and beta.
  */
 typedef struct smg_batch_s* smg_batch_t;

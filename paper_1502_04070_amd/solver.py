@@ -369,8 +369,8 @@ def _fill(h, level, tau, sigma):
 
 class Batch:
     """Many independent instances (sizes N_k = n0 2^L_k, coefficients beta_k)
-    solved together: one launch per stage for all of them, one captured graph
-    per iterate.  Several right-hand sides of one problem are several
+    solved together: one launch per stage for all of them, replayed from
+    captured graphs of one and of four iterates.  Several right-hand sides of one problem are several
     instances with equal (N, beta)."""
 
     def __init__(self, Ns, betas, smoother: str = "ne", tau: float | None = None, sigma: float = 0.8,
