@@ -129,6 +129,27 @@ struct CoarseJob {
   T tau[CC_MAX_LEVELS + 1], sigma[CC_MAX_LEVELS + 1];   // smoother damping per level
   const int* done;
 };
+// The coarse part of an iterate from a zero iterate is a linear map of the
+// restricted defect F of level Lc: x = K F.  K (column-major, n x n over the
+// lattice entries of level Lc: velocity 2 M^2, then pressure) is formed once
+// by the coarse-level kernel applied to unit vectors, and k_ccd applies it.
+template <class T>
+struct DenseJob {
+  const T* K;
+  int n, nu;              // lattice length of level Lc, its velocity part
+  const T* fu;
+  const T* fp;
+  T* xu;
+  T* xp;
+  const int* done;
+};
+constexpr int KD_MAX = 1024;   // largest lattice length given a dense map
+constexpr int KD_ROWS = 16;    // rows of K per workgroup (16 column phases of 16 rows)
+inline int ccd_blocks(int n) { return (n + KD_ROWS - 1) / KD_ROWS; }
+template <class T>
+void launch_ccd(const DenseJob<T>& J, hipStream_t s);
+template <class T>
+void launch_ccd_b(const JobArg<DenseJob<T>>& A, int nb, hipStream_t s);
 size_t coarse_cycle_lds(int n0, int Lc, size_t elem);
 template <class T>
 int launch_coarse_cycle(const CoarseJob<T>& J, hipStream_t s);

@@ -1662,6 +1662,97 @@ void launch_cc_b(const CoarseJob<T>* jobs, int njobs, size_t lds, int dom, hipSt
 template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, int, hipStream_t);
 template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// k_ccd: x = K F for the dense coarse map.  A workgroup forms KD_ROWS rows:
+// its 256 threads are 16 column phases of 16 rows, each thread adding the
+// columns of its phase (eight loads in flight at a time), then the phases'
+// sums are added in a fixed order.  F is staged in LDS by every workgroup.
+// In FP64 the sums are compensated (the product's rounding error by an FMA,
+// the addition's by the two-sum of Knuth), so that the map's rows, whose
+// terms cancel strongly for large beta, keep the accuracy of the level-by-
+// level computation.
+// ---------------------------------------------------------------------------
+// s + c += a b with the rounding errors of the product and the sum kept in c
+__device__ __forceinline__ void dot2_add(double a, double b, double& s, double& c) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double e = fma(a, b, -p);
+  const double t = s + p;
+  const double bb = t - s;
+  c += ((s - (t - bb)) + (p - bb)) + e;
+  s = t;
+}
+__device__ __forceinline__ void dot2_add(float a, float b, float& s, float&) { s += a * b; }
+template <class T>
+__device__ __forceinline__ void ccd_body(const DenseJob<T>& J, int rb) {
+  static_assert(KD_ROWS * 16 == 256, "256 threads: 16 phases of KD_ROWS rows");
+  __shared__ T sf[KD_MAX];
+  __shared__ T part[16][KD_ROWS + 1];
+  __shared__ T partc[16][KD_ROWS + 1];
+  const int tid = threadIdx.x, n = J.n, nu = J.nu;
+  const int dn = J.done ? *J.done : 0;
+  for (int e = tid; e < n; e += 256) sf[e] = e < nu ? J.fu[e] : J.fp[e - nu];
+  __syncthreads();
+  if (dn) return;   // uniform across the workgroup
+  const int r = tid % KD_ROWS, ph = tid / KD_ROWS;
+  const int row = rb * KD_ROWS + r;
+  T z = T(0), zc = T(0);
+  if (row < n) {
+    const T* k = J.K + row;
+    int q = ph;
+    for (; q + 16 * 7 < n; q += 16 * 8) {
+      T kv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kv[u] = k[(size_t)(q + 16 * u) * n];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dot2_add(kv[u], sf[q + 16 * u], z, zc);
+    }
+    for (; q < n; q += 16) dot2_add(k[(size_t)q * n], sf[q], z, zc);
+  }
+  part[ph][r] = z;
+  partc[ph][r] = zc;
+  __syncthreads();
+  const int rw = rb * KD_ROWS + tid;
+  if (tid < KD_ROWS && rw < n) {
+    T v = T(0), vc = T(0);
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      dot2_add(part[p][tid], T(1), v, vc);
+      vc += partc[p][tid];
+    }
+    v += vc;
+    if (rw < nu) J.xu[rw] = v;
+    else J.xp[rw - nu] = v;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_ccd(DenseJob<T> J) {
+  ccd_body<T>(J, blockIdx.x);
+}
+
+template <class T, bool PACK>
+__global__ __launch_bounds__(256) void k_ccd_b(const JobArg<DenseJob<T>> A) {
+  int tile;
+  const DenseJob<T> J = block_job<PACK>(A, (int)blockIdx.x, tile);
+  ccd_body<T>(J, tile);
+}
+
+template <class T>
+void launch_ccd(const DenseJob<T>& J, hipStream_t s) {
+  k_ccd<T><<<ccd_blocks(J.n), 256, 0, s>>>(J);
+}
+template void launch_ccd<double>(const DenseJob<double>&, hipStream_t);
+template void launch_ccd<float>(const DenseJob<float>&, hipStream_t);
+
+template <class T>
+void launch_ccd_b(const JobArg<DenseJob<T>>& A, int nb, hipStream_t s) {
+  if (A.n > 0) k_ccd_b<T, true><<<nb, 256, 0, s>>>(A);
+  else k_ccd_b<T, false><<<nb, 256, 0, s>>>(A);
+}
+template void launch_ccd_b<double>(const JobArg<DenseJob<double>>&, int, hipStream_t);
+template void launch_ccd_b<float>(const JobArg<DenseJob<float>>&, int, hipStream_t);
+
 size_t coarse_cycle_lds(int n0, int Lc, size_t elem) {
   size_t tot = 0;
   for (int l = 0; l <= Lc; ++l) {
