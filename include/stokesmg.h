@@ -127,7 +127,16 @@ const char* smg_last_error(void);
  * Shat^-1 arrays (Section 6, preconditioner), work vectors, and the inverse of
  * the coarsest-grid saddle matrix bordered by the mean-zero constraint
  * m^T p = 0, m_i = int phi_i (Section 3: level 0 is solved exactly).
- * Synchronous.  Errors: SMG_EINVAL, SMG_ENOMEM, SMG_ESINGULAR, SMG_EHIP.
+ * With the fused path and coarse levels (those the single-workgroup kernel
+ * handles, N <= coarse_max_n) below the finest, whose finest has at most 1024
+ * lattice entries (N <= 8 with n0 = 2), it also forms the dense coarse map:
+ * the coarse part of an iterate entered from a zero iterate is a linear map
+ * of the restricted defect, and its matrix (FP64 and FP32, formed by that
+ * kernel applied to unit vectors) replaces the level-by-level computation in
+ * the iterates of solves with rtol = 0 or rtol >= 1e-11 (its rounding leaves
+ * a relative residual floor of about 1e-12; tighter tolerances keep the
+ * kernel).  Synchronous.  Errors: SMG_EINVAL, SMG_ENOMEM, SMG_ESINGULAR,
+ * SMG_EHIP.
  */
 int smg_setup(int N, double beta, const smg_params* prm, smg_t* out);
 /* Frees the hierarchy and everything it owns; NULL is accepted (no-op). */
@@ -272,8 +281,9 @@ int smg_solve_mixed(smg_t h, const double* fu, const double* gp, double rtol, in
  * sigma.  The coarsest level (solved exactly) ignores them.  Captured
  * iterates of h are dropped and captured again by the next solve; a batch
  * that holds h (smg_batch_handle) plans and captures its iterates again at
- * its next solve.  Errors: SMG_EINVAL
- * (values not finite and > 0, bad level).
+ * its next solve.  A change on a level of the dense coarse map forms the map
+ * again (synchronous).  Errors: SMG_EINVAL (values not finite and > 0, bad
+ * level), SMG_EHIP.
  */
 int smg_set_damping(smg_t h, int level, double tau, double sigma);
 int smg_get_damping(smg_t h, int level, double* tau, double* sigma);
