@@ -333,7 +333,8 @@ DenseJob<T> dense_job(const smg_hier* H, Vec<T> x, Vec<T> f, const int* done) {
 
 // Column j of K is the coarse-level kernel's result for the j-th unit vector
 // of the lattice of level Lc (from a zero iterate): one batched launch with
-// a job per column, in the precision of the cycle that will use it.
+// a job per column, in the precision of the cycle that will use it; K is then
+// stored by rows.
 template <class T>
 int form_dense_map(smg_hier* H, T* K, hipStream_t s) {
   const int n = H->kn, nu = H->knu;
@@ -372,8 +373,20 @@ int form_dense_map(smg_hier* H, T* K, hipStream_t s) {
       rc = fail(SMG_EHIP, "dense coarse map upload");
     } else {
       launch_cc_b<T>(jd, n, coarse_cycle_lds(H->prm.n0, H->Lc, sizeof(T)), H->dom, s);
-      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         rc = fail(SMG_EHIP, "dense coarse map launch");
+      } else {
+        // the launch wrote K column by column; k_ccd reads it by rows
+        std::vector<T> col((size_t)n * n);
+        if (hipMemcpy(col.data(), K, sizeof(T) * col.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = fail(SMG_EHIP, "dense coarse map read-back");
+        } else {
+          for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) eye[(size_t)i * n + j] = col[(size_t)j * n + i];
+          if (hipMemcpy(K, eye.data(), sizeof(T) * eye.size(), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(SMG_EHIP, "dense coarse map upload");
+        }
+      }
     }
   }
   (void)hipStreamSynchronize(s);

@@ -130,7 +130,7 @@ struct CoarseJob {
   const int* done;
 };
 // The coarse part of an iterate from a zero iterate is a linear map of the
-// restricted defect F of level Lc: x = K F.  K (column-major, n x n over the
+// restricted defect F of level Lc: x = K F.  K (row-major, n x n over the
 // lattice entries of level Lc: velocity 2 M^2, then pressure) is formed once
 // by the coarse-level kernel applied to unit vectors, and k_ccd applies it.
 template <class T>
@@ -144,7 +144,7 @@ struct DenseJob {
   const int* done;
 };
 constexpr int KD_MAX = 1024;   // largest lattice length given a dense map
-constexpr int KD_ROWS = 16;    // rows of K per workgroup (16 column phases of 16 rows)
+constexpr int KD_ROWS = 4;     // rows of K per workgroup (one wave per row)
 inline int ccd_blocks(int n) { return (n + KD_ROWS - 1) / KD_ROWS; }
 template <class T>
 void launch_ccd(const DenseJob<T>& J, hipStream_t s);

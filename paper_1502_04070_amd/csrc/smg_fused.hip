@@ -1663,14 +1663,13 @@ template void launch_cc_b<double>(const CoarseJob<double>*, int, size_t, int, hi
 template void launch_cc_b<float>(const CoarseJob<float>*, int, size_t, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// k_ccd: x = K F for the dense coarse map.  A workgroup forms KD_ROWS rows:
-// its 256 threads are 16 column phases of 16 rows, each thread adding the
-// columns of its phase (eight loads in flight at a time), then the phases'
-// sums are added in a fixed order.  F is staged in LDS by every workgroup.
-// In FP64 the sums are compensated (the product's rounding error by an FMA,
-// the addition's by the two-sum of Knuth), so that the map's rows, whose
-// terms cancel strongly for large beta, keep the accuracy of the level-by-
-// level computation.
+// k_ccd: x = K F for the dense coarse map.  One wave per row of K (row-major):
+// the lanes take every 64th column, so that each load instruction reads 512
+// contiguous bytes, and the lanes' sums are added in a fixed tree.  F is
+// staged in LDS by every workgroup.  In FP64 the sums are compensated (the
+// product's rounding error by an FMA, the addition's by the two-sum of
+// Knuth), so that the map's rows, whose terms cancel strongly for large beta,
+// keep the accuracy of the level-by-level computation.
 // ---------------------------------------------------------------------------
 // s + c += a b with the rounding errors of the product and the sum kept in c
 __device__ __forceinline__ void dot2_add(double a, double b, double& s, double& c) {
@@ -1685,44 +1684,39 @@ __device__ __forceinline__ void dot2_add(double a, double b, double& s, double& 
 __device__ __forceinline__ void dot2_add(float a, float b, float& s, float&) { s += a * b; }
 template <class T>
 __device__ __forceinline__ void ccd_body(const DenseJob<T>& J, int rb) {
-  static_assert(KD_ROWS * 16 == 256, "256 threads: 16 phases of KD_ROWS rows");
+  static_assert(KD_ROWS * 64 == 256, "256 threads: one wave per row");
   __shared__ T sf[KD_MAX];
-  __shared__ T part[16][KD_ROWS + 1];
-  __shared__ T partc[16][KD_ROWS + 1];
-  const int tid = threadIdx.x, n = J.n, nu = J.nu;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n = J.n, nu = J.nu;
   const int dn = J.done ? *J.done : 0;
   for (int e = tid; e < n; e += 256) sf[e] = e < nu ? J.fu[e] : J.fp[e - nu];
   __syncthreads();
   if (dn) return;   // uniform across the workgroup
-  const int r = tid % KD_ROWS, ph = tid / KD_ROWS;
-  const int row = rb * KD_ROWS + r;
+  const int row = rb * KD_ROWS + w;
+  if (row >= n) return;   // no barrier follows
+  const T* k = J.K + (size_t)row * n;
   T z = T(0), zc = T(0);
-  if (row < n) {
-    const T* k = J.K + row;
-    int q = ph;
-    for (; q + 16 * 7 < n; q += 16 * 8) {
-      T kv[8];
+  int q = lane;
+  for (; q + 64 * 7 < n; q += 64 * 8) {
+    T kv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) kv[u] = k[(size_t)(q + 16 * u) * n];
+    for (int u = 0; u < 8; ++u) kv[u] = k[q + 64 * u];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) dot2_add(kv[u], sf[q + 16 * u], z, zc);
-    }
-    for (; q < n; q += 16) dot2_add(k[(size_t)q * n], sf[q], z, zc);
+    for (int u = 0; u < 8; ++u) dot2_add(kv[u], sf[q + 64 * u], z, zc);
   }
-  part[ph][r] = z;
-  partc[ph][r] = zc;
-  __syncthreads();
-  const int rw = rb * KD_ROWS + tid;
-  if (tid < KD_ROWS && rw < n) {
-    T v = T(0), vc = T(0);
+  for (; q < n; q += 64) dot2_add(k[q], sf[q], z, zc);
+  // lane sums in a fixed tree; each addition's error joins the correction
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      dot2_add(part[p][tid], T(1), v, vc);
-      vc += partc[p][tid];
-    }
-    v += vc;
-    if (rw < nu) J.xu[rw] = v;
-    else J.xp[rw - nu] = v;
+  for (int off = 32; off >= 1; off >>= 1) {
+    const T oz = __shfl_down(z, off, 64);
+    const T oc = __shfl_down(zc, off, 64);
+    dot2_add(oz, T(1), z, zc);
+    zc += oc;
+  }
+  if (lane == 0) {
+    const T v = z + zc;
+    if (row < nu) J.xu[row] = v;
+    else J.xp[row - nu] = v;
   }
 }
 
